@@ -1,0 +1,203 @@
+"""Benchmark: Lennard-Jones MD with neighbour lists, N = 10^6, one MI355X.
+
+Workload (the paper's LJ benchmark parameters, Tab. 7.2T1, with a 0.3 skin
+and a list rebuild every 10 steps): 100^3 simple-cubic lattice at density
+0.8442, Gaussian velocities at T* = 1 (seed 2), eps = sigma = m = 1,
+rc = 2.5 (energy shifted to zero at rc, so the reported drift measures the
+integration), skin 0.3, dt = 0.001, FP32 pair forces with FP64 positions,
+separations, energies and virial; PE and virial every 10 steps.
+
+A step is one full velocity-Verlet step of the whole path: fused kick+drift,
+(every 10th step) skin check + cell binning + reordering + neighbour-list
+build, force pass (with energy/virial on every 10th), KE reductions.
+Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the keys below).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s LJ N=1M + HBM GB/s; MLP vs LJ time at stated force RMSE"
+HBM_PEAK_GBS = 8000.0
+FORCE_SRC = os.path.join(ROOT, "paper_1704_03329_amd", "csrc", "lj.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lj_force_f32_n1m_traffic.txt")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def force_src_hash() -> str:
+    with open(FORCE_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per force launch from the committed counter summary, or None
+    if absent or taken on a different version of the force kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("force_source_sha256_16") != force_src_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(pos, box, rows: int):
+    """The FP64 all-pairs oracle on a bounded sample of the same workload:
+    forces for `rows` atoms against all N (one step's force work for them)."""
+    import numpy as np
+
+    from oracle import lj as olj
+
+    sample = np.sort(np.random.Generator(np.random.PCG64(7)).choice(pos.shape[0], rows, replace=False))
+    t0 = time.perf_counter()
+    olj.lj_forces(pos, box, 2.5, rows=sample)
+    dt = time.perf_counter() - t0
+    return {
+        "value": rows / dt,
+        "unit": "atom-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 all-pairs minimum-image LJ forces of {rows} random atoms against all "
+                  f"{pos.shape[0]} (numpy, single thread; host has {os.cpu_count()} cores); "
+                  f"{dt:.1f} s; velocity-Verlet updates not included",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n-side", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=192)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "domain decomposition is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mdinputs
+    from paper_1704_03329_amd import mdpl as C
+    from paper_1704_03329_amd.sim import LJSim
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n_side = args.n_side
+    d = mdinputs.lj_fluid(n_side, temperature=1.0, seed=2)
+    n = d["pos"].shape[0]
+    box = d["box"]
+    log(f"N={n} box={box[0]:.4f} building context")
+    sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp32", shift="cutoff",
+                max_nb=128)
+    state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    torch.cuda.synchronize()
+
+    log(f"warmup {args.warmup} steps")
+    sim.run(state, args.warmup, 10)
+    torch.cuda.synchronize()
+    st, flags, maxc = sim.check(raise_on_error=False)
+    if st != 0:
+        raise SystemExit(f"warmup flagged status {st} flags {flags}")
+
+    C.mdpl_set_timing(sim.handle, True)
+    C.mdpl_kernel_time(sim.handle, 0)  # reset
+    C.mdpl_kernel_time(sim.handle, 1)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    thermo = sim.run(state, args.steps, 10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    st, flags, maxc = sim.check(raise_on_error=False)
+    if st != 0:
+        raise SystemExit(f"timed run flagged status {st} flags {flags}")
+    f_ms, f_n = C.mdpl_kernel_time(sim.handle, 0)
+    fe_ms, fe_n = C.mdpl_kernel_time(sim.handle, 1)
+    C.mdpl_set_timing(sim.handle, False)
+    entries = C.mdpl_nlist_entries(sim.handle)
+    th = thermo.cpu().numpy()
+    etot = th[:, 0] + th[:, 1]
+    log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
+        f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}")
+
+    # algorithmic bytes of one plain force launch: per atom cnt (4) + own
+    # position (24, also the gathered neighbour positions, read once) + force
+    # (12 as float); per list entry its index (4)
+    alg_bytes = n * (4 + 24 + 12) + 4 * entries
+    avg_s = (f_ms / 1e3) / max(f_n, 1)
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = measured_traffic()
+
+    out = {
+        "metric": METRIC,
+        "value": n * args.steps / elapsed,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"LJ fluid N={n} ({n_side}^3 sc lattice, rho 0.8442, T*=1, seed 2), rc 2.5, "
+                        "skin 0.3, rebuild every 10 steps, dt 0.001, FP32 pair forces, FP64 "
+                        "positions/energy/virial, PE+virial every 10 steps",
+            "n_atoms": n,
+            "nlist_entries_per_atom": entries / n,
+            "precision": "FP32 pair force math and sums; FP64 positions, velocities, separations, "
+                         "cutoff test, energy, virial",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_lj_force<float,float,false>",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_us": avg_s * 1e6,
+            "launches": f_n,
+        },
+        "kernels_us": {
+            "force": avg_s * 1e6,
+            "force_energy_virial": (fe_ms / max(fe_n, 1)) * 1e3,
+        },
+        "energy_drift_per_atom": float(np.max(np.abs(etot - etot[0])) / n),
+        "hbm_gbs_force": achieved,
+    }
+    if not args.no_cpu_baseline:
+        log(f"oracle CPU baseline on {args.cpu_rows} atoms")
+        out["cpu_baseline"] = cpu_baseline(d["pos"], box, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

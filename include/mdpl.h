@@ -1,0 +1,209 @@
+/*
+ * mdpl: short-range molecular-dynamics pair loops on AMD Instinct MI355X
+ * (gfx950), behind a plain C ABI.
+ *
+ * The operations follow the problem statement of Saunders, Grant & Mueller,
+ * "A Domain Specific Language for Performance Portable Molecular Dynamics
+ * Algorithms" (arXiv:1704.03329): N particles with positions, velocities
+ * and mass in a periodic box (Sec. 3.1), a cutoff r_c and an extra shell
+ * delta for neighbour-list reuse (Eq. extended_cutoff), the Lennard-Jones
+ * pair loop (Eqs. LJpotential, LJforce), the velocity-Verlet particle loops
+ * (Alg. VelocityVerlet), the bond-order analysis (Sec. 4.1) and the
+ * common-neighbour analysis (Sec. 4.2).
+ *
+ * Conventions (all entry points):
+ *  - Every pointer argument is a DEVICE pointer unless its name ends in
+ *    _host.  Arrays are structure-of-arrays, contiguous, length n (the
+ *    caller's particle count, no padding).  Forces are float or double
+ *    according to mdpl_lj_params.precision.
+ *  - The caller owns every array and the workspace; the library allocates no
+ *    device memory.  Pointers must stay valid until the stream reaches the
+ *    enqueued work.
+ *  - Work is enqueued on the hipStream_t given at creation (or per call for
+ *    the analysis entry points) and the call returns at once.  Only
+ *    mdpl_check, mdpl_nlist_export and mdpl_kernel_time synchronise.
+ *  - Errors are returned as mdpl_status codes, never thrown.  Argument
+ *    errors are detected on the host before any device work is enqueued.
+ *    Errors found by kernels (capacity, skin, non-finite) raise flag bits
+ *    that mdpl_check reports.
+ *  - One mdpl_sim must not be used from two host threads at once.
+ */
+#ifndef MDPL_H
+#define MDPL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mdpl_status;
+#define MDPL_OK 0
+#define MDPL_EINVAL 1     /* null pointer, n <= 0, box <= 0, rc <= 0, skin < 0, dt <= 0, ... */
+#define MDPL_EBOX 2       /* fewer than 3 cells of side >= rc+skin along some axis */
+#define MDPL_ECAPACITY 3  /* a neighbour list had more entries than max_nb */
+#define MDPL_ESKIN 4      /* a particle moved >= skin/2 between two list builds */
+#define MDPL_ENONFINITE 5 /* a non-finite velocity appeared */
+#define MDPL_EHIP 6       /* a HIP runtime call failed; see mdpl_last_hip_error */
+#define MDPL_ESTATE 7     /* call out of order (e.g. forces before a build) */
+#define MDPL_EWORKSPACE 8 /* workspace too small or misaligned (256 B) */
+
+/* Flag bits reported by mdpl_check. */
+#define MDPL_FLAG_NL_OVERFLOW 1u
+#define MDPL_FLAG_SKIN 2u
+#define MDPL_FLAG_NONFINITE 4u
+
+/* Energy shift of the Lennard-Jones potential.
+ * NONE:   V = 4 eps [(s/r)^12 - (s/r)^6]            (V(2^(1/6) s) = -eps)
+ * PAPER:  V + eps, the form printed in Eq. LJpotential (with its +1/4)
+ * CUTOFF: V - V(rc), continuous at the cutoff
+ * Forces are identical in all modes. */
+#define MDPL_SHIFT_NONE 0
+#define MDPL_SHIFT_PAPER 1
+#define MDPL_SHIFT_CUTOFF 2
+
+/* Force precision.  FP64: every pair computed and accumulated in double,
+ * forces stored as double.  FP32: separations and the cutoff test in double,
+ * pair force in float, per-atom float sum, forces stored as float; energies
+ * and the virial are always double. */
+#define MDPL_FP64 0
+#define MDPL_FP32 1
+
+typedef struct {
+  int64_t n;          /* number of particles, 1 .. 2^26 */
+  double box[3];      /* periodic box [0,Lx) x [0,Ly) x [0,Lz) */
+  double rc;          /* interaction cutoff r_c (> 0) */
+  double skin;        /* extra shell delta = rbar_c - r_c (>= 0), Eq. extended_cutoff */
+  double eps, sigma;  /* Lennard-Jones parameters (> 0) */
+  double mass;        /* particle mass (> 0) */
+  double dt;          /* time step (> 0) */
+  int32_t reuse_every;/* rebuild the cell and neighbour lists every this many steps (>= 1) */
+  int32_t shift;      /* MDPL_SHIFT_* */
+  int32_t precision;  /* MDPL_FP64 or MDPL_FP32 */
+  int32_t max_nb;     /* neighbour-list capacity per particle (1 .. 1024) */
+} mdpl_lj_params;
+
+typedef struct mdpl_sim mdpl_sim;
+
+/* Human-readable name of a status code (static string). */
+const char* mdpl_status_string(mdpl_status s);
+
+/* Last hipError_t seen by any entry point of this process (0 if none). */
+int32_t mdpl_last_hip_error(void);
+
+/* ------------------------------------------------------------------ LJ state
+ * Bytes of device workspace needed for these parameters (cell list, sorted
+ * copies, neighbour list, reduction partials, flags).  Host only. */
+mdpl_status mdpl_workspace_bytes(const mdpl_lj_params* p, size_t* bytes_host);
+
+/* Create a simulation context on `workspace` (device, >= mdpl_workspace_bytes,
+ * 256-byte aligned).  `stream` is a hipStream_t (NULL = default stream).
+ * Validates p (MDPL_EINVAL / MDPL_EBOX); enqueues the clearing of the flags. */
+mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t workspace_bytes,
+                            void* stream, mdpl_sim** out_host);
+
+/* Release the host-side context (the workspace stays the caller's). */
+mdpl_status mdpl_sim_destroy(mdpl_sim* sim);
+
+/* Cell binning and neighbour-list construction for the given positions
+ * (Sec. 3.1: cells of side >= rc+skin, 27-cell stencil, list of every j != i
+ * with |r_i - r_j| < rc+skin under the minimum image).  Particles are
+ * counting-sorted by cell into workspace copies; the caller's arrays are not
+ * modified.  Positions should lie in [0, L); any value with
+ * -L/4 <= x < 5L/4 gives the same list as its folded image would under the
+ * minimum-image rule. */
+mdpl_status mdpl_build(mdpl_sim* sim, const double* x, const double* y, const double* z);
+
+/* Copy the list of the last mdpl_build as directed pairs (i, j) in the
+ * caller's particle indices, unordered.  Writes min(count, cap) pairs,
+ * returns the total in *count_host.  Synchronises the stream. */
+mdpl_status mdpl_nlist_export(mdpl_sim* sim, int32_t* i_out, int32_t* j_out, int64_t cap,
+                              int64_t* count_host);
+
+/* Lennard-Jones forces (Eq. LJforce, F_i = sum_j f(r_i, r_j), INC_ZERO)
+ * for positions x,y,z (caller order) using the list of the last mdpl_build;
+ * the positions may have moved by less than skin/2 since then.
+ * fx,fy,fz: float* or double* per precision, caller order, overwritten.
+ * pe_w: nullable, 2 doubles receiving the potential energy sum_{i<j} V and
+ * the virial sum_{i<j} r_ij . f_ij.  e_atom: nullable, n doubles receiving
+ * 1/2 sum_j V(r_ij). */
+mdpl_status mdpl_forces(mdpl_sim* sim, const double* x, const double* y, const double* z,
+                        void* fx, void* fy, void* fz, double* pe_w, double* e_atom);
+
+/* Reverse-mode derivative of the potential energy E(x) = sum_{i<j} V:
+ * g_i = grad_e[0] * dE/dr_i = -grad_e[0] * F_i, in double, caller order,
+ * using the list of the last mdpl_build.  grad_e: 1 double (device). */
+mdpl_status mdpl_lj_backward(mdpl_sim* sim, const double* x, const double* y, const double* z,
+                             const double* grad_e, double* gx, double* gy, double* gz);
+
+/* Integrate nsteps of velocity Verlet (Alg. VelocityVerlet): F(r0) first,
+ * then per step v += dt/(2m) F; r += dt v; F = forces(r); v += dt/(2m) F.
+ * The cell and neighbour lists are rebuilt at the start and after every
+ * reuse_every-th step.  At every rebuild the particles are reordered by cell
+ * IN PLACE in all ten arrays (positions folded into [0, L)), so that
+ * ids[k] always holds the original id of the particle in slot k.
+ * thermo: nullable; if sample_every > 0 it receives
+ * (nsteps / sample_every + 1) rows of 4 doubles: KE, PE, virial, and the
+ * largest displacement of any particle from its position at the list build,
+ * over the reuse periods completed so far; rows are taken at step 0 and
+ * every sample_every steps (KE after the second half kick).  On sampled
+ * steps the force pass also forms PE and the virial in FP64.  A displacement
+ * reaching skin/2 (a pair inside rc could be missing from the list; the
+ * extended-cutoff condition of Eq. extended_cutoff bounds it by
+ * n dt v_max) raises MDPL_FLAG_SKIN; see mdpl_check. */
+mdpl_status mdpl_run(mdpl_sim* sim, double* x, double* y, double* z, double* vx, double* vy,
+                     double* vz, void* fx, void* fy, void* fz, int32_t* ids, int64_t nsteps,
+                     int32_t sample_every, double* thermo);
+
+/* Synchronise the stream and read the device flags (MDPL_FLAG_* bits) and
+ * the largest neighbour count seen (so max_nb can be raised).  Returns
+ * MDPL_ECAPACITY, MDPL_ESKIN or MDPL_ENONFINITE if the matching bit is set
+ * (in that priority), else MDPL_OK.  Either output may be NULL. */
+mdpl_status mdpl_check(mdpl_sim* sim, uint32_t* flags_host, int32_t* max_count_host);
+
+/* Clear the device flags and the largest-count record (enqueued). */
+mdpl_status mdpl_clear_flags(mdpl_sim* sim);
+
+/* Kernel timing on the context's stream with HIP events.  When on, mdpl_run
+ * brackets every launch of the force kernels with an event pair.
+ * mdpl_kernel_time synchronises and returns the summed milliseconds and the
+ * number of launches for `which` = 0 (plain force pass) or 1 (force pass
+ * with energy and virial), then resets the record. */
+mdpl_status mdpl_set_timing(mdpl_sim* sim, int32_t on);
+mdpl_status mdpl_kernel_time(mdpl_sim* sim, int32_t which, double* ms_host, int64_t* launches_host);
+
+/* Number of neighbour-list entries of the current list (sum of the
+ * per-particle counts), after mdpl_build or mdpl_run.  Synchronises. */
+mdpl_status mdpl_nlist_entries(mdpl_sim* sim, int64_t* entries_host);
+
+/* ------------------------------------------------------- structure analysis
+ * Both analyses use bonds |r_i - r_j| < rc (minimum image, strict, tested
+ * in double exactly as (dx*dx + dy*dy) + dz*dz < rc*rc).  Outputs are in the
+ * caller's particle order.  Workspace as above; host-validated. */
+mdpl_status mdpl_analysis_workspace_bytes(int64_t n, const double* box_host, double rc,
+                                          int32_t max_nb, size_t* bytes_host);
+
+/* Steinhardt bond order (Sec. 4.1, Eqs. Qell and qellm; Algs. sph_I, sph_II):
+ * q4, q6 (float, required), q5 (nullable) and nnb (int32, bond count |N(i)|;
+ * Q_l = 0 when nnb = 0). */
+mdpl_status mdpl_boa(const double* x, const double* y, const double* z, int64_t n,
+                     const double* box_host, double rc, float* q4, float* q5, float* q6,
+                     int32_t* nnb, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Common-neighbour analysis (Sec. 4.2, Eqs. Ei and Ei_ordered; Algs. cna_I,
+ * cna_II, cna_III and max_cluster_size).  max_nb <= 32.  Per particle:
+ * nnb[i] = number of bonds (may exceed max_nb; then only the label is set,
+ * to OTHER), trip[i*max_nb + k] for k < min(nnb, max_nb) = the triplets of
+ * its bonds packed as (n_cn << 20) | (n_b << 10) | n_lcb, sorted ascending;
+ * label[i] = 0 other, 1 fcc, 2 hcp, 3 bcc. */
+mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t n,
+                     const double* box_host, double rc, int32_t max_nb, uint32_t* trip,
+                     int32_t* nnb, uint8_t* label, void* workspace, size_t workspace_bytes,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDPL_H */

@@ -1,0 +1,575 @@
+// C-ABI entry points of libmdpl (declared in include/mdpl.h).
+//
+// The host side validates arguments, carves the caller's workspace and
+// enqueues kernels on the context's stream.  It owns no device memory.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mdpl;
+
+namespace {
+
+int32_t g_last_hip_error = 0;
+
+#define HIP_TRY(expr)                           \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) {                     \
+      g_last_hip_error = (int32_t)e_;           \
+      return MDPL_EHIP;                         \
+    }                                           \
+  } while (0)
+
+struct Timing {
+  std::vector<hipEvent_t> ev[2];  // start/stop pairs, flattened
+};
+
+}  // namespace
+
+struct mdpl_sim {
+  mdpl_lj_params p;
+  hipStream_t st;
+  Grid g;
+  int64_t n, npad;
+  double r2ext;
+  LJConst c;
+  int fbytes;
+  SortBufs sort;
+  int32_t* cell_start;
+  int32_t* perm;         // sorted slot -> caller index of the last standalone build
+  int32_t* skeys;        // sorted keys (points into sort buffers)
+  double *sx, *sy, *sz;  // sorted positions (standalone) / alternate state (run)
+  double *avx, *avy, *avz;
+  void *afx, *afy, *afz;
+  int32_t* aids;
+  double *xb, *yb, *zb;  // positions at the last build (run)
+  NList nl;
+  int32_t* offsets;      // n + 1 (export)
+  double* partials;      // per-block partials
+  int nblk;
+  uint32_t* flags;
+  int32_t* maxcount;
+  double* max_disp;
+  double* pe_w_tmp;      // 2 doubles
+  bool built;
+  bool have_list;
+  bool timing;
+  Timing tm;
+};
+
+extern "C" {
+
+const char* mdpl_status_string(mdpl_status s) {
+  switch (s) {
+    case MDPL_OK: return "ok";
+    case MDPL_EINVAL: return "invalid argument";
+    case MDPL_EBOX: return "box too small for the cell grid (need 3 cells of side >= rc+skin per axis)";
+    case MDPL_ECAPACITY: return "neighbour-list capacity exceeded";
+    case MDPL_ESKIN: return "particles moved half the skin before a list rebuild";
+    case MDPL_ENONFINITE: return "non-finite velocity";
+    case MDPL_EHIP: return "HIP runtime error";
+    case MDPL_ESTATE: return "call out of order";
+    case MDPL_EWORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+int32_t mdpl_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"
+
+namespace {
+
+mdpl_status validate(const mdpl_lj_params* p) {
+  if (!p) return MDPL_EINVAL;
+  if (p->n <= 0 || p->n > (1ll << 26)) return MDPL_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!(p->box[k] > 0.0) || !isfinite(p->box[k])) return MDPL_EINVAL;
+  if (!(p->rc > 0.0) || !(p->skin >= 0.0) || !(p->eps > 0.0) || !(p->sigma > 0.0) ||
+      !(p->mass > 0.0) || !(p->dt > 0.0))
+    return MDPL_EINVAL;
+  if (!isfinite(p->rc) || !isfinite(p->skin) || !isfinite(p->dt)) return MDPL_EINVAL;
+  if (p->reuse_every < 1 || p->reuse_every > kMaxCycle) return MDPL_EINVAL;
+  if (p->shift < 0 || p->shift > 2) return MDPL_EINVAL;
+  if (p->precision != MDPL_FP64 && p->precision != MDPL_FP32) return MDPL_EINVAL;
+  if (p->max_nb < 1 || p->max_nb > 1024) return MDPL_EINVAL;
+  Grid g;
+  return make_grid(p->box, p->rc + p->skin, &g);
+}
+
+size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
+  const int64_t n = p->n;
+  const int64_t npad = div_up(n, 256) * 256;
+  const size_t fb = p->precision == MDPL_FP32 ? 4 : 8;
+  const int64_t nblk = div_up(n, 256);
+  size_t b = sort_bytes(n);
+  b += align256(4 * (size_t)(g.ncells + 1));   // cell_start
+  b += align256(4 * (size_t)n);                // perm
+  b += 3 * align256(8 * (size_t)n);            // sx, sy, sz
+  b += 3 * align256(8 * (size_t)n);            // avx..
+  b += 3 * align256(fb * (size_t)n);           // afx..
+  b += align256(4 * (size_t)n);                // aids
+  b += 3 * align256(8 * (size_t)n);            // xb..
+  b += align256(4 * (size_t)p->max_nb * (size_t)npad);  // nbr
+  b += align256(4 * (size_t)npad);             // cnt
+  b += align256(4 * (size_t)(n + 1));          // offsets
+  b += align256(8 * (size_t)(2 * nblk + 2));   // partials
+  b += align256(64);                           // flags, maxcount, max_disp, pe_w_tmp
+  return b;
+}
+
+template <typename T>
+T* take(char*& p, size_t bytes) {
+  T* r = (T*)p;
+  p += align256(bytes);
+  return r;
+}
+
+double shift_value(const mdpl_lj_params* p) {
+  if (p->shift == MDPL_SHIFT_PAPER) return p->eps;
+  if (p->shift == MDPL_SHIFT_CUTOFF) {
+    const double s2 = p->sigma * p->sigma / (p->rc * p->rc);
+    const double s6 = s2 * s2 * s2;
+    return -4.0 * p->eps * (s6 * s6 - s6);
+  }
+  return 0.0;
+}
+
+mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const double* z,
+                         void* fx, void* fy, void* fz, const int32_t* scatter, bool energy,
+                         double* e_atom, double* pe_w_dst, int kind, int timing_slot) {
+  ForceOut out;
+  out.fx = fx;
+  out.fy = fy;
+  out.fz = fz;
+  out.scatter = scatter;
+  out.e_atom = e_atom;
+  out.partials = s->partials;
+  out.scale = 1.0;
+  out.scale_dev = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (s->timing && timing_slot >= 0) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s->st));
+  }
+  int nb = 0;
+  HIP_TRY(lj_force(x, y, z, s->n, s->nl, s->c, kind, energy, out, s->st, &nb));
+  if (e1) {
+    HIP_TRY(hipEventRecord(e1, s->st));
+    s->tm.ev[timing_slot].push_back(e0);
+    s->tm.ev[timing_slot].push_back(e1);
+  }
+  if (energy && pe_w_dst) HIP_TRY(reduce_partials(s->partials, nb, 2, 2, pe_w_dst, 1.0, s->st));
+  return MDPL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdpl_status mdpl_workspace_bytes(const mdpl_lj_params* p, size_t* bytes) {
+  if (!bytes) return MDPL_EINVAL;
+  mdpl_status v = validate(p);
+  if (v != MDPL_OK) return v;
+  Grid g;
+  make_grid(p->box, p->rc + p->skin, &g);
+  *bytes = lj_ws_bytes(p, g);
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t bytes, void* stream,
+                            mdpl_sim** out) {
+  if (!out || !workspace) return MDPL_EINVAL;
+  mdpl_status v = validate(p);
+  if (v != MDPL_OK) return v;
+  if (((uintptr_t)workspace & 255) != 0) return MDPL_EWORKSPACE;
+  mdpl_sim* s = new (std::nothrow) mdpl_sim();
+  if (!s) return MDPL_EINVAL;
+  s->p = *p;
+  s->st = (hipStream_t)stream;
+  make_grid(p->box, p->rc + p->skin, &s->g);
+  if (bytes < lj_ws_bytes(p, s->g)) {
+    delete s;
+    return MDPL_EWORKSPACE;
+  }
+  s->n = p->n;
+  s->npad = div_up(p->n, 256) * 256;
+  const double rext = p->rc + p->skin;
+  s->r2ext = rext * rext;
+  s->fbytes = p->precision == MDPL_FP32 ? 4 : 8;
+  s->c.rc2 = p->rc * p->rc;
+  s->c.eps = p->eps;
+  s->c.sigma2 = p->sigma * p->sigma;
+  s->c.shift_v = shift_value(p);
+  for (int k = 0; k < 3; ++k) {
+    s->c.box[k] = p->box[k];
+    s->c.half[k] = 0.5 * p->box[k];
+    s->c.inv_box[k] = 1.0 / p->box[k];
+  }
+  const int64_t n = s->n;
+  char* w = (char*)workspace;
+  sort_carve(w, n, &s->sort);
+  s->cell_start = take<int32_t>(w, 4 * (size_t)(s->g.ncells + 1));
+  s->perm = take<int32_t>(w, 4 * (size_t)n);
+  s->sx = take<double>(w, 8 * (size_t)n);
+  s->sy = take<double>(w, 8 * (size_t)n);
+  s->sz = take<double>(w, 8 * (size_t)n);
+  s->avx = take<double>(w, 8 * (size_t)n);
+  s->avy = take<double>(w, 8 * (size_t)n);
+  s->avz = take<double>(w, 8 * (size_t)n);
+  s->afx = take<char>(w, s->fbytes * (size_t)n);
+  s->afy = take<char>(w, s->fbytes * (size_t)n);
+  s->afz = take<char>(w, s->fbytes * (size_t)n);
+  s->aids = take<int32_t>(w, 4 * (size_t)n);
+  s->xb = take<double>(w, 8 * (size_t)n);
+  s->yb = take<double>(w, 8 * (size_t)n);
+  s->zb = take<double>(w, 8 * (size_t)n);
+  s->nl.nbr = take<int32_t>(w, 4 * (size_t)p->max_nb * (size_t)s->npad);
+  s->nl.cnt = take<int32_t>(w, 4 * (size_t)s->npad);
+  s->nl.stride = s->npad;
+  s->nl.max_nb = p->max_nb;
+  s->nl.layout = 0;
+  s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
+  s->nblk = (int)div_up(n, 256);
+  s->partials = take<double>(w, 8 * (size_t)(2 * s->nblk + 2));
+  char* small = take<char>(w, 64);
+  s->flags = (uint32_t*)small;
+  s->maxcount = (int32_t*)(small + 4);
+  s->max_disp = (double*)(small + 8);
+  s->pe_w_tmp = (double*)(small + 16);
+  s->built = false;
+  s->have_list = false;
+  s->timing = false;
+  hipError_t e = hipMemsetAsync(small, 0, 64, s->st);
+  if (e != hipSuccess) {
+    g_last_hip_error = (int32_t)e;
+    delete s;
+    return MDPL_EHIP;
+  }
+  *out = s;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_sim_destroy(mdpl_sim* s) {
+  if (!s) return MDPL_EINVAL;
+  for (int k = 0; k < 2; ++k)
+    for (hipEvent_t e : s->tm.ev[k]) (void)hipEventDestroy(e);
+  delete s;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_build(mdpl_sim* s, const double* x, const double* y, const double* z) {
+  if (!s || !x || !y || !z) return MDPL_EINVAL;
+  int32_t *skeys, *svals;
+  HIP_TRY(bin_particles(x, y, z, s->n, s->g, s->sort, s->cell_start, &skeys, &svals, s->st));
+  HIP_TRY(hipMemcpyAsync(s->perm, svals, 4 * (size_t)s->n, hipMemcpyDeviceToDevice, s->st));
+  s->skeys = skeys;
+  HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, false, s->st));
+  HIP_TRY(build_nlist(s->sx, s->sy, s->sz, skeys, s->cell_start, s->n, s->g, s->r2ext, s->nl,
+                      s->flags, s->maxcount, s->st));
+  s->built = true;
+  s->have_list = true;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_nlist_export(mdpl_sim* s, int32_t* i_out, int32_t* j_out, int64_t cap,
+                              int64_t* count_host) {
+  if (!s || !count_host || cap < 0 || (cap > 0 && (!i_out || !j_out))) return MDPL_EINVAL;
+  if (!s->built) return MDPL_ESTATE;
+  HIP_TRY(exclusive_scan(s->nl.cnt, s->offsets, s->n, s->sort.blocksums, true, s->st));
+  if (cap > 0) HIP_TRY(export_pairs(s->nl, s->perm, s->offsets, s->n, i_out, j_out, cap, s->st));
+  int32_t total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, s->offsets + s->n, 4, hipMemcpyDeviceToHost, s->st));
+  HIP_TRY(hipStreamSynchronize(s->st));
+  *count_host = total;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_nlist_entries(mdpl_sim* s, int64_t* entries) {
+  if (!s || !entries) return MDPL_EINVAL;
+  if (!s->have_list) return MDPL_ESTATE;
+  HIP_TRY(exclusive_scan(s->nl.cnt, s->offsets, s->n, s->sort.blocksums, true, s->st));
+  int32_t total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, s->offsets + s->n, 4, hipMemcpyDeviceToHost, s->st));
+  HIP_TRY(hipStreamSynchronize(s->st));
+  *entries = total;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_forces(mdpl_sim* s, const double* x, const double* y, const double* z, void* fx,
+                        void* fy, void* fz, double* pe_w, double* e_atom) {
+  if (!s || !x || !y || !z || !fx || !fy || !fz) return MDPL_EINVAL;
+  if (!s->built) return MDPL_ESTATE;
+  HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, false, s->st));
+  const bool energy = pe_w != nullptr || e_atom != nullptr;
+  return launch_force(s, s->sx, s->sy, s->sz, fx, fy, fz, s->perm, energy, e_atom, pe_w,
+                      s->p.precision, -1);
+}
+
+mdpl_status mdpl_lj_backward(mdpl_sim* s, const double* x, const double* y, const double* z,
+                             const double* grad_e, double* gx, double* gy, double* gz) {
+  if (!s || !x || !y || !z || !grad_e || !gx || !gy || !gz) return MDPL_EINVAL;
+  if (!s->built) return MDPL_ESTATE;
+  HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, false, s->st));
+  ForceOut out;
+  out.fx = gx;
+  out.fy = gy;
+  out.fz = gz;
+  out.scatter = s->perm;
+  out.e_atom = nullptr;
+  out.partials = s->partials;
+  out.scale = -1.0;
+  out.scale_dev = grad_e;
+  // FP64 arithmetic for the FP64 context, FP32 pair math for the FP32 one;
+  // the gradient is stored in double either way
+  const int kind = s->p.precision == MDPL_FP64 ? 2 : 3;
+  HIP_TRY(lj_force(s->sx, s->sy, s->sz, s->n, s->nl, s->c, kind, false, out, s->st, nullptr));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_check(mdpl_sim* s, uint32_t* flags_host, int32_t* max_count_host) {
+  if (!s) return MDPL_EINVAL;
+  uint32_t f = 0;
+  int32_t m = 0;
+  HIP_TRY(hipMemcpyAsync(&f, s->flags, 4, hipMemcpyDeviceToHost, s->st));
+  HIP_TRY(hipMemcpyAsync(&m, s->maxcount, 4, hipMemcpyDeviceToHost, s->st));
+  HIP_TRY(hipStreamSynchronize(s->st));
+  if (flags_host) *flags_host = f;
+  if (max_count_host) *max_count_host = m;
+  if (f & MDPL_FLAG_NL_OVERFLOW) return MDPL_ECAPACITY;
+  if (f & MDPL_FLAG_SKIN) return MDPL_ESKIN;
+  if (f & MDPL_FLAG_NONFINITE) return MDPL_ENONFINITE;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_clear_flags(mdpl_sim* s) {
+  if (!s) return MDPL_EINVAL;
+  HIP_TRY(hipMemsetAsync(s->flags, 0, 16, s->st));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_set_timing(mdpl_sim* s, int32_t on) {
+  if (!s) return MDPL_EINVAL;
+  s->timing = on != 0;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_kernel_time(mdpl_sim* s, int32_t which, double* ms, int64_t* launches) {
+  if (!s || which < 0 || which > 1) return MDPL_EINVAL;
+  HIP_TRY(hipStreamSynchronize(s->st));
+  double tot = 0.0;
+  std::vector<hipEvent_t>& v = s->tm.ev[which];
+  for (size_t k = 0; k + 1 < v.size(); k += 2) {
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, v[k], v[k + 1]));
+    tot += t;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = (int64_t)(v.size() / 2);
+  for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  v.clear();
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, double* vy,
+                     double* vz, void* fx, void* fy, void* fz, int32_t* ids, int64_t nsteps,
+                     int32_t sample_every, double* thermo) {
+  if (!s || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids) return MDPL_EINVAL;
+  if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
+  const int64_t n = s->n;
+  const int prec = s->p.precision;
+  const int ns = s->p.reuse_every;
+  const double dt = s->p.dt;
+  const double h = dt / (2.0 * s->p.mass);
+  const double half_skin = 0.5 * s->p.skin;
+  const double ke_scale = 0.5 * s->p.mass;
+  StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
+  StateArrays alt{s->sx, s->sy, s->sz, s->avx, s->avy, s->avz, s->afx, s->afy, s->afz, s->aids};
+  StateArrays cur = user, other = alt;
+  bool have_ref = false;
+  s->built = false;  // the standalone build is overwritten
+
+  auto rebuild = [&]() -> mdpl_status {
+    if (have_ref) {
+      int nb = 0;
+      HIP_TRY(disp_partials(cur.x, cur.y, cur.z, s->xb, s->yb, s->zb, n, s->partials, s->st, &nb));
+      HIP_TRY(skin_check(s->partials, nb, half_skin, s->max_disp, s->flags, s->st));
+    }
+    int32_t *skeys, *svals;
+    HIP_TRY(bin_particles(cur.x, cur.y, cur.z, n, s->g, s->sort, s->cell_start, &skeys, &svals,
+                          s->st));
+    HIP_TRY(reorder_state(cur, svals, n, s->fbytes, s->p.box, other, s->xb, s->yb, s->zb, s->st));
+    StateArrays t = cur;
+    cur = other;
+    other = t;
+    HIP_TRY(build_nlist(cur.x, cur.y, cur.z, skeys, s->cell_start, n, s->g, s->r2ext, s->nl,
+                        s->flags, s->maxcount, s->st));
+    have_ref = true;
+    s->have_list = true;
+    return MDPL_OK;
+  };
+  auto row = [&](int64_t step) { return thermo + 4 * (step / sample_every); };
+  auto sampled = [&](int64_t step) { return sample_every > 0 && step % sample_every == 0; };
+
+  mdpl_status r = rebuild();
+  if (r != MDPL_OK) return r;
+  r = launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr, sampled(0), nullptr,
+                   sampled(0) ? row(0) + 1 : nullptr, prec, -1);
+  if (r != MDPL_OK) return r;
+  if (sampled(0)) {
+    int nb = 0;
+    HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
+                    h, dt, 3, true, s->partials, s->flags, s->st, &nb));
+    HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(0), ke_scale, s->st));
+    HIP_TRY(hipMemcpyAsync(row(0) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
+  }
+  for (int64_t step = 1; step <= nsteps; ++step) {
+    const bool ke = step > 1 && sampled(step - 1);
+    int nb = 0;
+    HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
+                    h, dt, step == 1 ? 0 : 1, ke, s->partials, s->flags, s->st, &nb));
+    if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(step - 1), ke_scale, s->st));
+    if (step % ns == 0) {
+      r = rebuild();
+      if (r != MDPL_OK) return r;
+    }
+    const bool en = sampled(step);
+    r = launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr, en, nullptr,
+                     en ? row(step) + 1 : nullptr, prec, en ? 1 : 0);
+    if (r != MDPL_OK) return r;
+    if (en) HIP_TRY(hipMemcpyAsync(row(step) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
+  }
+  if (nsteps > 0) {
+    const bool ke = sampled(nsteps);
+    int nb = 0;
+    HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
+                    h, dt, 2, ke, s->partials, s->flags, s->st, &nb));
+    if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(nsteps), ke_scale, s->st));
+  }
+  // close the last reuse period
+  {
+    int nb = 0;
+    HIP_TRY(disp_partials(cur.x, cur.y, cur.z, s->xb, s->yb, s->zb, n, s->partials, s->st, &nb));
+    HIP_TRY(skin_check(s->partials, nb, half_skin, s->max_disp, s->flags, s->st));
+  }
+  if (cur.x != user.x) {
+    const size_t d8 = 8 * (size_t)n, fb = (size_t)s->fbytes * n;
+    HIP_TRY(hipMemcpyAsync(user.x, cur.x, d8, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.y, cur.y, d8, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.z, cur.z, d8, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.vx, cur.vx, d8, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.vy, cur.vy, d8, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.vz, cur.vz, d8, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.fx, cur.fx, fb, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.fy, cur.fy, fb, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.fz, cur.fz, fb, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(hipMemcpyAsync(user.ids, cur.ids, 4 * (size_t)n, hipMemcpyDeviceToDevice, s->st));
+  }
+  return MDPL_OK;
+}
+
+// ------------------------------------------------------------ analysis
+static size_t analysis_bytes(int64_t n, const Grid& g, int max_nb) {
+  size_t b = sort_bytes(n);
+  b += align256(4 * (size_t)(g.ncells + 1));
+  b += align256(4 * (size_t)n);          // perm
+  b += 3 * align256(8 * (size_t)n);      // sorted positions
+  b += align256(4 * (size_t)n * (size_t)max_nb);
+  b += align256(4 * (size_t)n);          // cnt
+  b += align256(64);
+  return b;
+}
+
+static mdpl_status analysis_prep(const double* x, const double* y, const double* z, int64_t n,
+                                 const double* box, double rc, int max_nb, void* ws, size_t bytes,
+                                 hipStream_t st, Grid* g, SortBufs* sb, int32_t** cs,
+                                 int32_t** perm, double** sx, double** sy, double** sz,
+                                 int32_t** skeys, NList* nl, uint32_t** small) {
+  if (!x || !y || !z || !box || !ws || n <= 0 || n > (1ll << 26)) return MDPL_EINVAL;
+  if (!(rc > 0.0) || !isfinite(rc) || max_nb < 1 || max_nb > 1024) return MDPL_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!(box[k] > 0.0) || !isfinite(box[k])) return MDPL_EINVAL;
+  if (((uintptr_t)ws & 255) != 0) return MDPL_EWORKSPACE;
+  mdpl_status v = make_grid(box, rc, g);
+  if (v != MDPL_OK) return v;
+  if (bytes < analysis_bytes(n, *g, max_nb)) return MDPL_EWORKSPACE;
+  char* w = (char*)ws;
+  sort_carve(w, n, sb);
+  *cs = take<int32_t>(w, 4 * (size_t)(g->ncells + 1));
+  *perm = take<int32_t>(w, 4 * (size_t)n);
+  *sx = take<double>(w, 8 * (size_t)n);
+  *sy = take<double>(w, 8 * (size_t)n);
+  *sz = take<double>(w, 8 * (size_t)n);
+  nl->nbr = take<int32_t>(w, 4 * (size_t)n * (size_t)max_nb);
+  nl->cnt = take<int32_t>(w, 4 * (size_t)n);
+  nl->stride = n;
+  nl->max_nb = max_nb;
+  nl->layout = 1;
+  *small = take<uint32_t>(w, 64);
+  int32_t* svals;
+  HIP_TRY(bin_particles(x, y, z, n, *g, *sb, *cs, skeys, &svals, st));
+  HIP_TRY(hipMemcpyAsync(*perm, svals, 4 * (size_t)n, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(gather_positions(x, y, z, *perm, n, *sx, *sy, *sz, box, false, st));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_analysis_workspace_bytes(int64_t n, const double* box, double rc, int32_t max_nb,
+                                          size_t* bytes) {
+  if (!box || !bytes || n <= 0 || n > (1ll << 26) || !(rc > 0.0) || max_nb < 1 || max_nb > 1024)
+    return MDPL_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!(box[k] > 0.0) || !isfinite(box[k])) return MDPL_EINVAL;
+  Grid g;
+  mdpl_status v = make_grid(box, rc, &g);
+  if (v != MDPL_OK) return v;
+  *bytes = analysis_bytes(n, g, max_nb);
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_boa(const double* x, const double* y, const double* z, int64_t n,
+                     const double* box, double rc, float* q4, float* q5, float* q6, int32_t* nnb,
+                     void* ws, size_t bytes, void* stream) {
+  if (!q4 || !q6 || !nnb) return MDPL_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Grid g;
+  SortBufs sb;
+  int32_t *cs, *perm, *skeys;
+  double *sx, *sy, *sz;
+  NList nl;
+  uint32_t* small;
+  // the bond-order pass walks the cells itself: no list is stored
+  mdpl_status v = analysis_prep(x, y, z, n, box, rc, 1, ws, bytes, st, &g, &sb, &cs, &perm, &sx,
+                                &sy, &sz, &skeys, &nl, &small);
+  if (v != MDPL_OK) return v;
+  HIP_TRY(boa_q(sx, sy, sz, skeys, cs, perm, n, g, rc * rc, q4, q5, q6, nnb, st));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t n,
+                     const double* box, double rc, int32_t max_nb, uint32_t* trip, int32_t* nnb,
+                     uint8_t* label, void* ws, size_t bytes, void* stream) {
+  if (!trip || !nnb || !label || max_nb < 1 || max_nb > 32) return MDPL_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Grid g;
+  SortBufs sb;
+  int32_t *cs, *perm, *skeys;
+  double *sx, *sy, *sz;
+  NList nl;
+  uint32_t* small;
+  mdpl_status v = analysis_prep(x, y, z, n, box, rc, max_nb, ws, bytes, st, &g, &sb, &cs, &perm,
+                                &sx, &sy, &sz, &skeys, &nl, &small);
+  if (v != MDPL_OK) return v;
+  HIP_TRY(hipMemsetAsync(small, 0, 64, st));
+  HIP_TRY(build_nlist(sx, sy, sz, skeys, cs, n, g, rc * rc, nl, small, (int32_t*)(small + 1), st));
+  HIP_TRY(cna_signatures(nl, perm, n, trip, nnb, label, max_nb, st));
+  return MDPL_OK;
+}
+
+}  // extern "C"

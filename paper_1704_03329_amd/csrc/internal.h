@@ -1,0 +1,141 @@
+// Internal declarations shared by the translation units of libmdpl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mdpl.h"
+
+namespace mdpl {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;                       // keys per thread per tile
+constexpr int kSortTile = kSortThreads * kSortItems; // keys per tile
+constexpr int kReduceThreads = 256;                  // block size of reducing kernels
+constexpr int kMaxCycle = 4096;                      // largest reuse_every
+
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Cell grid: ncell[k] = floor(L_k / (r * (1 + 1e-10))) cells of side L_k / ncell[k].
+struct Grid {
+  int nc[3];
+  int ncells;
+  double inv_side[3];
+  double box[3];
+};
+
+// Returns MDPL_EBOX if fewer than 3 cells fit along some axis.
+mdpl_status make_grid(const double box[3], double r, Grid* g);
+
+// Radix-sort scratch for n keys.
+struct SortBufs {
+  int32_t* keys[2];
+  int32_t* vals[2];
+  int32_t* hist;      // kRadixBins * ntiles, then its block sums
+  int32_t* blocksums; // scan scratch
+  int64_t n;
+  int ntiles;
+};
+size_t sort_bytes(int64_t n);
+void sort_carve(char*& p, int64_t n, SortBufs* s);
+
+// Sort particles by cell: keys computed from (folded) positions, values =
+// particle index.  On return keys_out/vals_out point at the sorted arrays
+// (one of the two ping-pong buffers) and cell_start[0..ncells] is filled.
+hipError_t bin_particles(const double* x, const double* y, const double* z, int64_t n,
+                         const Grid& g, SortBufs& s, int32_t* cell_start, int32_t** keys_out,
+                         int32_t** vals_out, hipStream_t st);
+
+// Exclusive prefix sum of n int32 values into out (may alias in).  Uses
+// blocksums scratch of at least div_up(n, 1024) + 1 entries.  Also writes
+// the total to out[n] if write_total.
+hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* blocksums,
+                          bool write_total, hipStream_t st);
+
+// Gathers: dst[k] = src[idx[k]] for double / float / int arrays.
+hipError_t gather_positions(const double* x, const double* y, const double* z, const int32_t* idx,
+                            int64_t n, double* ox, double* oy, double* oz, const double* box,
+                            bool fold, hipStream_t st);
+
+struct StateArrays {
+  double *x, *y, *z, *vx, *vy, *vz;
+  void *fx, *fy, *fz;
+  int32_t* ids;
+};
+// dst[s] = src[idx[s]] for all ten arrays, positions folded into the box;
+// xb/yb/zb (nullable) receive a copy of the folded positions.
+hipError_t reorder_state(const StateArrays& src, const int32_t* idx, int64_t n, int fbytes,
+                         const double* box, StateArrays& dst, double* xb, double* yb, double* zb,
+                         hipStream_t st);
+
+// Neighbour list (ELL).  layout 0: column-major nbr[m * stride + i];
+// layout 1: row-major nbr[i * max_nb + m].  Entries are sorted-slot indices.
+struct NList {
+  int32_t* nbr;
+  int32_t* cnt;
+  int64_t stride;
+  int max_nb;
+  int layout;
+};
+hipError_t build_nlist(const double* sx, const double* sy, const double* sz,
+                       const int32_t* skeys, const int32_t* cell_start, int64_t n, const Grid& g,
+                       double r2, NList nl, uint32_t* flags, int32_t* maxcount, hipStream_t st);
+
+// Lennard-Jones pair constants.
+struct LJConst {
+  double rc2, eps, sigma2, shift_v;  // shift_v added to every pair energy
+  double box[3], half[3], inv_box[3];
+};
+
+struct ForceOut {
+  void *fx, *fy, *fz;     // force arrays (float or double)
+  const int32_t* scatter; // nullable: slot s writes to scatter[s]
+  double* e_atom;         // nullable (scattered like forces)
+  double* partials;       // per-block {pe, w} when energy is on
+  double scale;           // multiplies the stored force (backward: -grad)
+  const double* scale_dev;// nullable: device scalar multiplying the stored force
+};
+hipError_t lj_force(const double* x, const double* y, const double* z, int64_t n, const NList& nl,
+                    const LJConst& c, int precision, bool energy, const ForceOut& out,
+                    hipStream_t st, int* nblocks_out);
+
+// Velocity Verlet particle loops on the sorted state (INC on v and r).
+//   mode 0: v += h F ; r += dt v                          (first step)
+//   mode 1: v += h F ; [KE] ; v += h F ; r += dt v         (fused end+start)
+//   mode 2: v += h F ; [KE]                               (final half kick)
+//   mode 3: KE only
+hipError_t vv_step(double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                   const void* fx, const void* fy, const void* fz, int precision, int64_t n,
+                   double h, double dt, int mode, bool ke, double* ke_partials, uint32_t* flags,
+                   hipStream_t st, int* nblocks_out);
+
+// out[0] = sum of partials[k * stride + comp] over k, fixed order, one block.
+hipError_t reduce_partials(const double* partials, int nblocks, int stride, int ncomp,
+                           double* out, double scale, hipStream_t st);
+
+// Per-block maxima of |r - r_build|^2 into partials.
+hipError_t disp_partials(const double* x, const double* y, const double* z, const double* xb,
+                         const double* yb, const double* zb, int64_t n, double* partials,
+                         hipStream_t st, int* nblocks_out);
+
+// d = sqrt(max partials); *max_disp = max(*max_disp, d); flags |= SKIN if d >= half_skin.
+hipError_t skin_check(const double* partials, int nblocks, double half_skin, double* max_disp,
+                      uint32_t* flags, hipStream_t st);
+
+// Analysis kernels on sorted positions.
+hipError_t boa_q(const double* sx, const double* sy, const double* sz, const int32_t* skeys,
+                 const int32_t* cell_start, const int32_t* perm, int64_t n, const Grid& g,
+                 double rc2, float* q4, float* q5, float* q6, int32_t* nnb, hipStream_t st);
+
+hipError_t cna_signatures(const NList& nl, const int32_t* perm, int64_t n, uint32_t* trip,
+                          int32_t* nnb, uint8_t* label, int max_out, hipStream_t st);
+
+hipError_t export_pairs(const NList& nl, const int32_t* perm, const int32_t* offsets, int64_t n,
+                        int32_t* i_out, int32_t* j_out, int64_t cap, hipStream_t st);
+
+hipError_t sum_counts(const int32_t* cnt, int64_t n, int32_t* blocksums, hipStream_t st);
+
+}  // namespace mdpl

@@ -1,0 +1,278 @@
+// Lennard-Jones pair loop and velocity-Verlet particle loops.
+//
+// Force (Eq. LJforce): f_ij = 48 eps [(s^2/d2)^7 - 1/2 (s^2/d2)^4] / s^2 * dr_ij,
+// dr_ij = r_i - r_j (min image), summed over the neighbour list of i and
+// written once per particle (gather only, no atomics: the paper's choice of
+// looping over all ordered pairs and writing to the first particle, Sec. 2).
+// The cutoff test d2 < rc^2 uses the same FP64 separation and the same
+// uncontracted d2 as the list build, so the set of interacting pairs equals
+// the all-pairs definition.  The min image uses k = rint(dx / L) and one
+// fused multiply-add dx - k L, which rounds exactly like the conditional
+// dx -/+ L.
+//
+// Precision (FP32 mode): the separation and the test in FP64, the pair force
+// in FP32 from the rounded separation, FP32 per-particle sum.  Energy and
+// virial (sampled steps) are formed per pair in FP64 and reduced per block
+// with wavefront shuffles into FP64 partials; a single-block pass sums the
+// partials in a fixed order, so results are reproducible run to run.
+//
+// Potential energy: PE = 1/2 sum over ordered pairs (each unordered pair
+// once), e_i = 1/2 sum_j V(r_ij); virial W = 1/2 sum over ordered pairs of
+// dr . f.
+#include "device_util.h"
+#include "internal.h"
+
+namespace mdpl {
+
+__device__ __forceinline__ double img(double d, double L, double invL) {
+  return __builtin_fma(-__builtin_rint(d * invL), L, d);
+}
+
+__device__ __forceinline__ double sq_sum(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// MT: pair-force arithmetic type; OT: stored force type.
+template <typename MT, typename OT, bool ENERGY>
+__global__ __launch_bounds__(256) void k_lj_force(const double* __restrict__ x,
+                                                  const double* __restrict__ y,
+                                                  const double* __restrict__ z, int64_t n,
+                                                  NList nl, LJConst c, ForceOut out) {
+  __shared__ double sh[4];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  MT ax = 0, ay = 0, az = 0;
+  double e = 0.0, w = 0.0;
+  if (s < n) {
+    const double xi = x[s], yi = y[s], zi = z[s];
+    const int cnt = nl.cnt[s];
+    const int32_t* __restrict__ col = nl.nbr + s;
+    const MT sig2 = (MT)c.sigma2;
+    const MT c48 = (MT)(48.0 * c.eps);
+    for (int m = 0; m < cnt; ++m) {
+      const int32_t t = col[(int64_t)m * nl.stride];
+      const double dx = img(xi - x[t], c.box[0], c.inv_box[0]);
+      const double dy = img(yi - y[t], c.box[1], c.inv_box[1]);
+      const double dz = img(zi - z[t], c.box[2], c.inv_box[2]);
+      const double d2 = sq_sum(dx, dy, dz);
+      const bool in = d2 < c.rc2;
+      if (ENERGY) {
+        // pair energy and virial in FP64 for the sampled steps
+        const double inv = 1.0 / d2;
+        const double s2 = c.sigma2 * inv;
+        const double s6 = s2 * s2 * s2;
+        const double g = 48.0 * c.eps * inv * s6 * (s6 - 0.5);
+        const double v = 4.0 * c.eps * (s6 * s6 - s6) + c.shift_v;
+        const double gg = in ? g : 0.0;
+        e += in ? 0.5 * v : 0.0;
+        w += 0.5 * gg * d2;
+        ax += (MT)(gg * dx);
+        ay += (MT)(gg * dy);
+        az += (MT)(gg * dz);
+      } else {
+        MT inv;
+        if constexpr (sizeof(MT) == 4)
+          inv = __builtin_amdgcn_rcpf((float)d2);
+        else
+          inv = 1.0 / d2;
+        const MT s2 = sig2 * inv;
+        const MT s6 = s2 * s2 * s2;
+        MT g = c48 * inv * s6 * (s6 - (MT)0.5);
+        g = in ? g : (MT)0;
+        ax += g * (MT)dx;
+        ay += g * (MT)dy;
+        az += g * (MT)dz;
+      }
+    }
+    double scale = out.scale;
+    if (out.scale_dev) scale *= *out.scale_dev;
+    const int64_t o = out.scatter ? (int64_t)out.scatter[s] : s;
+    ((OT*)out.fx)[o] = (OT)((double)ax * scale);
+    ((OT*)out.fy)[o] = (OT)((double)ay * scale);
+    ((OT*)out.fz)[o] = (OT)((double)az * scale);
+    if (ENERGY && out.e_atom) out.e_atom[o] = e;
+  }
+  if (ENERGY) {
+    const double pe = block_sum256(e, sh);
+    const double ww = block_sum256(w, sh);
+    if (threadIdx.x == 0) {
+      out.partials[2 * blockIdx.x] = pe;
+      out.partials[2 * blockIdx.x + 1] = ww;
+    }
+  }
+}
+
+template <typename MT, typename OT>
+static void launch_force(bool energy, unsigned nb, hipStream_t st, const double* x,
+                         const double* y, const double* z, int64_t n, const NList& nl,
+                         const LJConst& c, const ForceOut& out) {
+  if (energy)
+    hipLaunchKernelGGL((k_lj_force<MT, OT, true>), dim3(nb), dim3(256), 0, st, x, y, z, n, nl, c,
+                       out);
+  else
+    hipLaunchKernelGGL((k_lj_force<MT, OT, false>), dim3(nb), dim3(256), 0, st, x, y, z, n, nl, c,
+                       out);
+}
+
+hipError_t lj_force(const double* x, const double* y, const double* z, int64_t n, const NList& nl,
+                    const LJConst& c, int precision, bool energy, const ForceOut& out,
+                    hipStream_t st, int* nblocks_out) {
+  const unsigned nb = (unsigned)div_up(n, 256);
+  if (nblocks_out) *nblocks_out = (int)nb;
+  // precision: 0 FP64 math/double out, 1 FP32 math/float out,
+  //            2 FP64 math/double out (backward), 3 FP32 math/double out (backward)
+  switch (precision) {
+    case 0:
+    case 2:
+      launch_force<double, double>(energy, nb, st, x, y, z, n, nl, c, out);
+      break;
+    case 1:
+      launch_force<float, float>(energy, nb, st, x, y, z, n, nl, c, out);
+      break;
+    default:
+      launch_force<float, double>(energy, nb, st, x, y, z, n, nl, c, out);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ velocity Verlet
+// Listing position_update / velocity_update: v += F dt/(2m); r += dt v.
+template <typename FT>
+__global__ __launch_bounds__(256) void k_vv(double* __restrict__ x, double* __restrict__ y,
+                                            double* __restrict__ z, double* __restrict__ vx,
+                                            double* __restrict__ vy, double* __restrict__ vz,
+                                            const FT* __restrict__ fx, const FT* __restrict__ fy,
+                                            const FT* __restrict__ fz, int64_t n, double h,
+                                            double dt, int mode, int ke, double* ke_part,
+                                            uint32_t* flags) {
+#pragma clang fp contract(off)
+  __shared__ double sh[4];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double k = 0.0;
+  if (s < n) {
+    double a = vx[s], b = vy[s], cc = vz[s];
+    if (mode != 3) {
+      const double gx = h * (double)fx[s], gy = h * (double)fy[s], gz = h * (double)fz[s];
+      a = a + gx;
+      b = b + gy;
+      cc = cc + gz;
+      if (mode == 1 || mode == 2) k = (a * a + b * b) + cc * cc;
+      if (mode == 1) {
+        a = a + gx;
+        b = b + gy;
+        cc = cc + gz;
+      }
+      if (mode != 2) {
+        x[s] = x[s] + dt * a;
+        y[s] = y[s] + dt * b;
+        z[s] = z[s] + dt * cc;
+      }
+      vx[s] = a;
+      vy[s] = b;
+      vz[s] = cc;
+      const double m2 = (a * a + b * b) + cc * cc;
+      if (!(m2 < 1e300)) atomicOr(flags, MDPL_FLAG_NONFINITE);
+    } else {
+      k = (a * a + b * b) + cc * cc;
+    }
+  }
+  if (ke) {
+    const double t = block_sum256(k, sh);
+    if (threadIdx.x == 0) ke_part[blockIdx.x] = t;
+  }
+}
+
+hipError_t vv_step(double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                   const void* fx, const void* fy, const void* fz, int precision, int64_t n,
+                   double h, double dt, int mode, bool ke, double* ke_partials, uint32_t* flags,
+                   hipStream_t st, int* nblocks_out) {
+  const unsigned nb = (unsigned)div_up(n, 256);
+  if (nblocks_out) *nblocks_out = (int)nb;
+  if (precision == 1)
+    hipLaunchKernelGGL(k_vv<float>, dim3(nb), dim3(256), 0, st, x, y, z, vx, vy, vz,
+                       (const float*)fx, (const float*)fy, (const float*)fz, n, h, dt, mode,
+                       ke ? 1 : 0, ke_partials, flags);
+  else
+    hipLaunchKernelGGL(k_vv<double>, dim3(nb), dim3(256), 0, st, x, y, z, vx, vy, vz,
+                       (const double*)fx, (const double*)fy, (const double*)fz, n, h, dt, mode,
+                       ke ? 1 : 0, ke_partials, flags);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ reductions
+// out[c] = scale * sum_k partials[k*stride + c], fixed order, one block.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ p, int nb,
+                                                         int stride, int ncomp, double* out,
+                                                         double scale) {
+  __shared__ double sh[4];
+  for (int comp = 0; comp < ncomp; ++comp) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) v += p[(int64_t)k * stride + comp];
+    const double t = block_sum256(v, sh);
+    if (threadIdx.x == 0) out[comp] = scale * t;
+  }
+}
+
+hipError_t reduce_partials(const double* partials, int nblocks, int stride, int ncomp,
+                           double* out, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nblocks, stride,
+                     ncomp, out, scale);
+  return hipGetLastError();
+}
+
+}  // namespace mdpl
+
+namespace mdpl {
+
+// ------------------------------------------------------------ skin check
+// Largest squared displacement since the last list build, per block.
+__global__ __launch_bounds__(256) void k_disp_partials(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ xb, const double* __restrict__ yb, const double* __restrict__ zb,
+    int64_t n, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0;
+  if (s < n) {
+    const double a = x[s] - xb[s], b = y[s] - yb[s], c = z[s] - zb[s];
+    d = a * a + b * b + c * c;
+    if (!(d < 1e300)) d = 1e300;
+  }
+  const double m = block_max256(d, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+hipError_t disp_partials(const double* x, const double* y, const double* z, const double* xb,
+                         const double* yb, const double* zb, int64_t n, double* partials,
+                         hipStream_t st, int* nblocks_out) {
+  const unsigned nb = (unsigned)div_up(n, 256);
+  *nblocks_out = (int)nb;
+  hipLaunchKernelGGL(k_disp_partials, dim3(nb), dim3(256), 0, st, x, y, z, xb, yb, zb, n, partials);
+  return hipGetLastError();
+}
+
+// max over the partials -> displacement; record the largest; flag when it
+// reaches half the skin (a pair inside rc could then be missing from the list).
+__global__ __launch_bounds__(256) void k_skin_check(const double* __restrict__ part, int nb,
+                                                    double half_skin, double* max_disp,
+                                                    uint32_t* flags) {
+  __shared__ double sh[4];
+  double v = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) v = part[k] > v ? part[k] : v;
+  const double m2 = block_max256(v, sh);
+  if (threadIdx.x == 0) {
+    const double d = sqrt(m2);
+    if (d > *max_disp) *max_disp = d;
+    if (d >= half_skin) atomicOr(flags, MDPL_FLAG_SKIN);
+  }
+}
+
+hipError_t skin_check(const double* partials, int nblocks, double half_skin, double* max_disp,
+                      uint32_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_skin_check, dim3(1), dim3(256), 0, st, partials, nblocks, half_skin,
+                     max_disp, flags);
+  return hipGetLastError();
+}
+
+}  // namespace mdpl
