@@ -44,12 +44,12 @@ struct mdpl_sim {
   int32_t* cell_start;
   int32_t* perm;         // sorted slot -> caller index of the last standalone build
   int32_t* skeys;        // sorted keys (points into sort buffers)
+  TileList tl;
   double *sx, *sy, *sz;  // sorted positions (standalone) / alternate state (run)
   double *avx, *avy, *avz;
   void *afx, *afy, *afz;
   int32_t* aids;
   double *xb, *yb, *zb;  // positions at the last build (run)
-  NList nl;
   int32_t* offsets;      // n + 1 (export)
   double* partials;      // per-block partials
   int nblk;
@@ -100,23 +100,46 @@ mdpl_status validate(const mdpl_lj_params* p) {
   if (p->precision != MDPL_FP64 && p->precision != MDPL_FP32) return MDPL_EINVAL;
   if (p->max_nb < 1 || p->max_nb > 1024) return MDPL_EINVAL;
   Grid g;
-  return make_grid(p->box, p->rc + p->skin, &g);
+  int unit[3] = {1, 1, 1};
+  return make_grid(p->box, p->rc + p->skin, unit, &g);
+}
+
+// Brick of cells handled by one workgroup of the LJ kernels: the largest
+// cube (3, 2 or 1 cells) whose tile, (B+2)^3 cells at the mean occupancy,
+// fills at most 80% of the LDS tile; workgroup size ~1.15x its particles.
+void lj_grid(const mdpl_lj_params* p, Grid* g, int* threads) {
+  int unit[3] = {1, 1, 1};
+  make_grid(p->box, p->rc + p->skin, unit, g);
+  const double per_cell = (double)p->n / ((double)g->nc[0] * g->nc[1] * g->nc[2]);
+  int b = 1;
+  for (int cand = 3; cand >= 1; --cand) {
+    const double tile = (cand + 2.0) * (cand + 2.0) * (cand + 2.0) * per_cell;
+    if (tile <= 0.8 * kTileMax) {
+      b = cand;
+      break;
+    }
+  }
+  int brick[3] = {b, b, b};
+  make_grid(p->box, p->rc + p->skin, brick, g);
+  int t = (int)(1.15 * g->V * per_cell + 0.5);
+  t = ((t + 63) / 64) * 64;
+  *threads = t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
 
 size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   const int64_t n = p->n;
   const int64_t npad = div_up(n, 256) * 256;
   const size_t fb = p->precision == MDPL_FP32 ? 4 : 8;
-  const int64_t nblk = div_up(n, 256);
+  const int64_t nblk = div_up(n, 256) > g.nbricks ? div_up(n, 256) : g.nbricks;
   size_t b = sort_bytes(n);
-  b += align256(4 * (size_t)(g.ncells + 1));   // cell_start
+  b += align256(4 * (size_t)(g.nkeys + 1));    // cell_start
   b += align256(4 * (size_t)n);                // perm
   b += 3 * align256(8 * (size_t)n);            // sx, sy, sz
   b += 3 * align256(8 * (size_t)n);            // avx..
   b += 3 * align256(fb * (size_t)n);           // afx..
   b += align256(4 * (size_t)n);                // aids
   b += 3 * align256(8 * (size_t)n);            // xb..
-  b += align256(4 * (size_t)p->max_nb * (size_t)npad);  // nbr
+  b += align256(2 * (size_t)((p->max_nb + 3) & ~3) * (size_t)npad);  // nbr (16-bit tile indices)
   b += align256(4 * (size_t)npad);             // cnt
   b += align256(4 * (size_t)(n + 1));          // offsets
   b += align256(8 * (size_t)(2 * nblk + 2));   // partials
@@ -160,7 +183,7 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
     HIP_TRY(hipEventRecord(e0, s->st));
   }
   int nb = 0;
-  HIP_TRY(lj_force(x, y, z, s->n, s->nl, s->c, kind, energy, out, s->st, &nb));
+  HIP_TRY(lj_force(x, y, z, s->cell_start, s->g, s->tl, s->c, kind, energy, out, s->st, &nb));
   if (e1) {
     HIP_TRY(hipEventRecord(e1, s->st));
     s->tm.ev[timing_slot].push_back(e0);
@@ -179,7 +202,8 @@ mdpl_status mdpl_workspace_bytes(const mdpl_lj_params* p, size_t* bytes) {
   mdpl_status v = validate(p);
   if (v != MDPL_OK) return v;
   Grid g;
-  make_grid(p->box, p->rc + p->skin, &g);
+  int threads;
+  lj_grid(p, &g, &threads);
   *bytes = lj_ws_bytes(p, g);
   return MDPL_OK;
 }
@@ -194,7 +218,8 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   if (!s) return MDPL_EINVAL;
   s->p = *p;
   s->st = (hipStream_t)stream;
-  make_grid(p->box, p->rc + p->skin, &s->g);
+  int threads = 64;
+  lj_grid(p, &s->g, &threads);
   if (bytes < lj_ws_bytes(p, s->g)) {
     delete s;
     return MDPL_EWORKSPACE;
@@ -216,7 +241,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   const int64_t n = s->n;
   char* w = (char*)workspace;
   sort_carve(w, n, &s->sort);
-  s->cell_start = take<int32_t>(w, 4 * (size_t)(s->g.ncells + 1));
+  s->cell_start = take<int32_t>(w, 4 * (size_t)(s->g.nkeys + 1));
   s->perm = take<int32_t>(w, 4 * (size_t)n);
   s->sx = take<double>(w, 8 * (size_t)n);
   s->sy = take<double>(w, 8 * (size_t)n);
@@ -231,13 +256,14 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->xb = take<double>(w, 8 * (size_t)n);
   s->yb = take<double>(w, 8 * (size_t)n);
   s->zb = take<double>(w, 8 * (size_t)n);
-  s->nl.nbr = take<int32_t>(w, 4 * (size_t)p->max_nb * (size_t)s->npad);
-  s->nl.cnt = take<int32_t>(w, 4 * (size_t)s->npad);
-  s->nl.stride = s->npad;
-  s->nl.max_nb = p->max_nb;
-  s->nl.layout = 0;
+  const int max_nb4 = (p->max_nb + 3) & ~3;
+  s->tl.nbr = take<uint64_t>(w, 2 * (size_t)max_nb4 * (size_t)s->npad);
+  s->tl.cnt = take<int32_t>(w, 4 * (size_t)s->npad);
+  s->tl.stride = s->npad;
+  s->tl.max_nb = p->max_nb;
+  s->tl.threads = threads;
   s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
-  s->nblk = (int)div_up(n, 256);
+  s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
   s->partials = take<double>(w, 8 * (size_t)(2 * s->nblk + 2));
   char* small = take<char>(w, 64);
   s->flags = (uint32_t*)small;
@@ -272,8 +298,8 @@ mdpl_status mdpl_build(mdpl_sim* s, const double* x, const double* y, const doub
   HIP_TRY(hipMemcpyAsync(s->perm, svals, 4 * (size_t)s->n, hipMemcpyDeviceToDevice, s->st));
   s->skeys = skeys;
   HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, false, s->st));
-  HIP_TRY(build_nlist(s->sx, s->sy, s->sz, skeys, s->cell_start, s->n, s->g, s->r2ext, s->nl,
-                      s->flags, s->maxcount, s->st));
+  HIP_TRY(build_tile_nlist(s->sx, s->sy, s->sz, skeys, s->cell_start, s->g, s->r2ext, s->tl,
+                           s->flags, s->maxcount, s->st));
   s->built = true;
   s->have_list = true;
   return MDPL_OK;
@@ -283,8 +309,10 @@ mdpl_status mdpl_nlist_export(mdpl_sim* s, int32_t* i_out, int32_t* j_out, int64
                               int64_t* count_host) {
   if (!s || !count_host || cap < 0 || (cap > 0 && (!i_out || !j_out))) return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
-  HIP_TRY(exclusive_scan(s->nl.cnt, s->offsets, s->n, s->sort.blocksums, true, s->st));
-  if (cap > 0) HIP_TRY(export_pairs(s->nl, s->perm, s->offsets, s->n, i_out, j_out, cap, s->st));
+  HIP_TRY(exclusive_scan(s->tl.cnt, s->offsets, s->n, s->sort.blocksums, true, s->st));
+  if (cap > 0)
+    HIP_TRY(export_tile_pairs(s->tl, s->cell_start, s->g, s->perm, s->offsets, i_out, j_out, cap,
+                              s->st));
   int32_t total = 0;
   HIP_TRY(hipMemcpyAsync(&total, s->offsets + s->n, 4, hipMemcpyDeviceToHost, s->st));
   HIP_TRY(hipStreamSynchronize(s->st));
@@ -295,7 +323,7 @@ mdpl_status mdpl_nlist_export(mdpl_sim* s, int32_t* i_out, int32_t* j_out, int64
 mdpl_status mdpl_nlist_entries(mdpl_sim* s, int64_t* entries) {
   if (!s || !entries) return MDPL_EINVAL;
   if (!s->have_list) return MDPL_ESTATE;
-  HIP_TRY(exclusive_scan(s->nl.cnt, s->offsets, s->n, s->sort.blocksums, true, s->st));
+  HIP_TRY(exclusive_scan(s->tl.cnt, s->offsets, s->n, s->sort.blocksums, true, s->st));
   int32_t total = 0;
   HIP_TRY(hipMemcpyAsync(&total, s->offsets + s->n, 4, hipMemcpyDeviceToHost, s->st));
   HIP_TRY(hipStreamSynchronize(s->st));
@@ -307,7 +335,7 @@ mdpl_status mdpl_forces(mdpl_sim* s, const double* x, const double* y, const dou
                         void* fy, void* fz, double* pe_w, double* e_atom) {
   if (!s || !x || !y || !z || !fx || !fy || !fz) return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
-  HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, false, s->st));
+  HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   const bool energy = pe_w != nullptr || e_atom != nullptr;
   return launch_force(s, s->sx, s->sy, s->sz, fx, fy, fz, s->perm, energy, e_atom, pe_w,
                       s->p.precision, -1);
@@ -317,7 +345,7 @@ mdpl_status mdpl_lj_backward(mdpl_sim* s, const double* x, const double* y, cons
                              const double* grad_e, double* gx, double* gy, double* gz) {
   if (!s || !x || !y || !z || !grad_e || !gx || !gy || !gz) return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
-  HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, false, s->st));
+  HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   ForceOut out;
   out.fx = gx;
   out.fy = gy;
@@ -330,7 +358,8 @@ mdpl_status mdpl_lj_backward(mdpl_sim* s, const double* x, const double* y, cons
   // FP64 arithmetic for the FP64 context, FP32 pair math for the FP32 one;
   // the gradient is stored in double either way
   const int kind = s->p.precision == MDPL_FP64 ? 2 : 3;
-  HIP_TRY(lj_force(s->sx, s->sy, s->sz, s->n, s->nl, s->c, kind, false, out, s->st, nullptr));
+  HIP_TRY(lj_force(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, s->c, kind, false, out, s->st,
+                   nullptr));
   return MDPL_OK;
 }
 
@@ -409,8 +438,8 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
     StateArrays t = cur;
     cur = other;
     other = t;
-    HIP_TRY(build_nlist(cur.x, cur.y, cur.z, skeys, s->cell_start, n, s->g, s->r2ext, s->nl,
-                        s->flags, s->maxcount, s->st));
+    HIP_TRY(build_tile_nlist(cur.x, cur.y, cur.z, skeys, s->cell_start, s->g, s->r2ext, s->tl,
+                             s->flags, s->maxcount, s->st));
     have_ref = true;
     s->have_list = true;
     return MDPL_OK;
@@ -478,7 +507,7 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
 // ------------------------------------------------------------ analysis
 static size_t analysis_bytes(int64_t n, const Grid& g, int max_nb) {
   size_t b = sort_bytes(n);
-  b += align256(4 * (size_t)(g.ncells + 1));
+  b += align256(4 * (size_t)(g.nkeys + 1));
   b += align256(4 * (size_t)n);          // perm
   b += 3 * align256(8 * (size_t)n);      // sorted positions
   b += align256(4 * (size_t)n * (size_t)max_nb);
@@ -497,12 +526,13 @@ static mdpl_status analysis_prep(const double* x, const double* y, const double*
   for (int k = 0; k < 3; ++k)
     if (!(box[k] > 0.0) || !isfinite(box[k])) return MDPL_EINVAL;
   if (((uintptr_t)ws & 255) != 0) return MDPL_EWORKSPACE;
-  mdpl_status v = make_grid(box, rc, g);
+  int unit[3] = {1, 1, 1};
+  mdpl_status v = make_grid(box, rc, unit, g);
   if (v != MDPL_OK) return v;
   if (bytes < analysis_bytes(n, *g, max_nb)) return MDPL_EWORKSPACE;
   char* w = (char*)ws;
   sort_carve(w, n, sb);
-  *cs = take<int32_t>(w, 4 * (size_t)(g->ncells + 1));
+  *cs = take<int32_t>(w, 4 * (size_t)(g->nkeys + 1));
   *perm = take<int32_t>(w, 4 * (size_t)n);
   *sx = take<double>(w, 8 * (size_t)n);
   *sy = take<double>(w, 8 * (size_t)n);
@@ -527,7 +557,8 @@ mdpl_status mdpl_analysis_workspace_bytes(int64_t n, const double* box, double r
   for (int k = 0; k < 3; ++k)
     if (!(box[k] > 0.0) || !isfinite(box[k])) return MDPL_EINVAL;
   Grid g;
-  mdpl_status v = make_grid(box, rc, &g);
+  int unit[3] = {1, 1, 1};
+  mdpl_status v = make_grid(box, rc, unit, &g);
   if (v != MDPL_OK) return v;
   *bytes = analysis_bytes(n, g, max_nb);
   return MDPL_OK;

@@ -13,8 +13,8 @@
 
 namespace mdpl {
 
-mdpl_status make_grid(const double box[3], double r, Grid* g) {
-  g->ncells = 1;
+mdpl_status make_grid(const double box[3], double r, const int brick[3], Grid* g) {
+  g->nbricks = 1;
   for (int k = 0; k < 3; ++k) {
     double side_min = r * (1.0 + 1e-10);
     double q = floor(box[k] / side_min);
@@ -23,8 +23,16 @@ mdpl_status make_grid(const double box[3], double r, Grid* g) {
     g->nc[k] = (int)q;
     g->inv_side[k] = q / box[k];
     g->box[k] = box[k];
-    g->ncells *= g->nc[k];
+    int b = brick[k] < 1 ? 1 : brick[k];
+    if (b > g->nc[k]) b = g->nc[k];
+    g->B[k] = b;
+    g->nb[k] = (g->nc[k] + b - 1) / b;
+    g->nbricks *= g->nb[k];
   }
+  g->V = g->B[0] * g->B[1] * g->B[2];
+  const long long nk = (long long)g->nbricks * g->V;
+  if (nk > (1ll << 30)) return MDPL_EBOX;
+  g->nkeys = (int)nk;
   return MDPL_OK;
 }
 
@@ -68,7 +76,7 @@ __global__ void k_cell_keys(const double* __restrict__ x, const double* __restri
   int cx = cell_coord(x[i], g.box[0], g.inv_side[0], g.nc[0]);
   int cy = cell_coord(y[i], g.box[1], g.inv_side[1], g.nc[1]);
   int cz = cell_coord(z[i], g.box[2], g.inv_side[2], g.nc[2]);
-  keys[i] = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+  keys[i] = cell_key(g, cx, cy, cz);
   vals[i] = (int32_t)i;
 }
 
@@ -236,7 +244,7 @@ hipError_t bin_particles(const double* x, const double* y, const double* z, int6
   const unsigned nb = (unsigned)div_up(n, 256);
   hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, st, x, y, z, n, g, s.keys[0], s.vals[0]);
   int bits = 1;
-  while ((1ll << bits) < (long long)g.ncells) ++bits;
+  while ((1ll << bits) < (long long)g.nkeys) ++bits;
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   int cur = 0;
   const int64_t hn = (int64_t)kRadixBins * s.ntiles;
@@ -250,7 +258,7 @@ hipError_t bin_particles(const double* x, const double* y, const double* z, int6
                        s.vals[cur], n, shift, s.ntiles, s.hist, s.keys[cur ^ 1], s.vals[cur ^ 1]);
     cur ^= 1;
   }
-  hipLaunchKernelGGL(k_cell_start, dim3(nb), dim3(256), 0, st, s.keys[cur], n, g.ncells,
+  hipLaunchKernelGGL(k_cell_start, dim3(nb), dim3(256), 0, st, s.keys[cur], n, g.nkeys,
                      cell_start);
   *keys_out = s.keys[cur];
   *vals_out = s.vals[cur];
@@ -281,6 +289,45 @@ hipError_t gather_positions(const double* x, const double* y, const double* z, c
                             bool do_fold, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, x, y, z, idx,
                      n, ox, oy, oz, box[0], box[1], box[2], do_fold ? 1 : 0);
+  return hipGetLastError();
+}
+
+// Positions of the last build's slots, each moved to the periodic image
+// nearest the centre of the cell it was binned in (the images the tiles
+// assume), whatever image the caller passes.
+__global__ void k_gather_canonical(const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ z, const int32_t* __restrict__ idx,
+                                   const int32_t* __restrict__ skeys, int64_t n, Grid g,
+                                   double* __restrict__ ox, double* __restrict__ oy,
+                                   double* __restrict__ oz) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int key = skeys[s];
+  const int brick = key / g.V, local = key - brick * g.V;
+  const int bx = brick % g.nb[0], by = (brick / g.nb[0]) % g.nb[1], bz = brick / (g.nb[0] * g.nb[1]);
+  const int cx = bx * g.B[0] + local % g.B[0];
+  const int cy = by * g.B[1] + (local / g.B[0]) % g.B[1];
+  const int cz = bz * g.B[2] + local / (g.B[0] * g.B[1]);
+  const int32_t j = idx[s];
+  const double p[3] = {x[j], y[j], z[j]};
+  const int c[3] = {cx, cy, cz};
+  double q[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double L = g.box[k];
+    const double centre = ((double)c[k] + 0.5) / g.inv_side[k];
+    q[k] = p[k] + L * rint((centre - p[k]) / L);
+  }
+  ox[s] = q[0];
+  oy[s] = q[1];
+  oz[s] = q[2];
+}
+
+hipError_t gather_canonical(const double* x, const double* y, const double* z, const int32_t* idx,
+                            const int32_t* skeys, int64_t n, const Grid& g, double* ox, double* oy,
+                            double* oz, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_canonical, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, x, y, z,
+                     idx, skeys, n, g, ox, oy, oz);
   return hipGetLastError();
 }
 

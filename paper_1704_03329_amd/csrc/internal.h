@@ -19,16 +19,32 @@ constexpr int kMaxCycle = 4096;                      // largest reuse_every
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Cell grid: ncell[k] = floor(L_k / (r * (1 + 1e-10))) cells of side L_k / ncell[k].
+// Cell grid: nc[k] = floor(L_k / (r (1 + 1e-10))) cells of side L_k / nc[k]
+// per axis, grouped into bricks of B[0] x B[1] x B[2] cells (the last brick
+// along an axis may be partial).  Cell keys are brick-major:
+//   key = brick * V + (lz * B[1] + ly) * B[0] + lx,
+//   brick = (bz * nb[1] + by) * nb[0] + bx,  V = B[0] B[1] B[2],
+// so that sorting particles by key makes every brick a contiguous range.
+// With B = (1,1,1) the key is the plain x-fastest cell index.
 struct Grid {
   int nc[3];
-  int ncells;
+  int B[3];
+  int nb[3];
+  int V;
+  int nbricks;
+  int nkeys;  // nbricks * V
   double inv_side[3];
   double box[3];
 };
 
 // Returns MDPL_EBOX if fewer than 3 cells fit along some axis.
-mdpl_status make_grid(const double box[3], double r, Grid* g);
+mdpl_status make_grid(const double box[3], double r, const int brick[3], Grid* g);
+
+__host__ __device__ inline int cell_key(const Grid& g, int cx, int cy, int cz) {
+  const int bx = cx / g.B[0], by = cy / g.B[1], bz = cz / g.B[2];
+  const int lx = cx - bx * g.B[0], ly = cy - by * g.B[1], lz = cz - bz * g.B[2];
+  return ((bz * g.nb[1] + by) * g.nb[0] + bx) * g.V + (lz * g.B[1] + ly) * g.B[0] + lx;
+}
 
 // Radix-sort scratch for n keys.
 struct SortBufs {
@@ -60,6 +76,12 @@ hipError_t gather_positions(const double* x, const double* y, const double* z, c
                             int64_t n, double* ox, double* oy, double* oz, const double* box,
                             bool fold, hipStream_t st);
 
+// Like gather_positions, but each position is moved to the periodic image
+// nearest the centre of its cell in the sorted keys skeys.
+hipError_t gather_canonical(const double* x, const double* y, const double* z, const int32_t* idx,
+                            const int32_t* skeys, int64_t n, const Grid& g, double* ox, double* oy,
+                            double* oz, hipStream_t st);
+
 struct StateArrays {
   double *x, *y, *z, *vx, *vy, *vz;
   void *fx, *fy, *fz;
@@ -71,8 +93,9 @@ hipError_t reorder_state(const StateArrays& src, const int32_t* idx, int64_t n, 
                          const double* box, StateArrays& dst, double* xb, double* yb, double* zb,
                          hipStream_t st);
 
-// Neighbour list (ELL).  layout 0: column-major nbr[m * stride + i];
-// layout 1: row-major nbr[i * max_nb + m].  Entries are sorted-slot indices.
+// Neighbour list (ELL) of the analysis passes: row-major nbr[i * max_nb + m]
+// of sorted-slot indices; cnt[i] is the true count (may exceed max_nb).
+// Requires a grid with B = (1,1,1).
 struct NList {
   int32_t* nbr;
   int32_t* cnt;
@@ -83,6 +106,31 @@ struct NList {
 hipError_t build_nlist(const double* sx, const double* sy, const double* sz,
                        const int32_t* skeys, const int32_t* cell_start, int64_t n, const Grid& g,
                        double r2, NList nl, uint32_t* flags, int32_t* maxcount, hipStream_t st);
+
+// Tiled neighbour list of the LJ path.  One workgroup per brick stages the
+// positions of the brick's (B+2)^3-cell neighbourhood (its "tile") in LDS;
+// entries are 16-bit tile-local indices packed four to a 64-bit word, the
+// words column-major: entry m of slot s is 16-bit lane (m & 3) of
+// nbr[(m >> 2) * stride + s].  The last word of a list is padded with
+// kTileDummy, a tile slot that holds a position far outside the box.
+constexpr int kTileMax = 3200;              // tile slots (LDS)
+constexpr int kTileDummy = kTileMax - 1;    // padding slot
+constexpr int kTileCap = kTileMax - 1;      // particles a tile can hold
+constexpr int kTileCells = 125;             // B <= 3 per axis
+struct TileList {
+  uint64_t* nbr;
+  int32_t* cnt;     // clamped to max_nb
+  int64_t stride;   // words per group row (>= n)
+  int max_nb;       // multiple of 4
+  int threads;      // workgroup size of the tile kernels
+};
+hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
+                            const int32_t* skeys, const int32_t* cell_start, const Grid& g,
+                            double r2, TileList tl, uint32_t* flags, int32_t* maxcount,
+                            hipStream_t st);
+hipError_t export_tile_pairs(const TileList& tl, const int32_t* cell_start, const Grid& g,
+                             const int32_t* perm, const int32_t* offsets, int32_t* i_out,
+                             int32_t* j_out, int64_t cap, hipStream_t st);
 
 // Lennard-Jones pair constants.
 struct LJConst {
@@ -98,9 +146,10 @@ struct ForceOut {
   double scale;           // multiplies the stored force (backward: -grad)
   const double* scale_dev;// nullable: device scalar multiplying the stored force
 };
-hipError_t lj_force(const double* x, const double* y, const double* z, int64_t n, const NList& nl,
-                    const LJConst& c, int precision, bool energy, const ForceOut& out,
-                    hipStream_t st, int* nblocks_out);
+// Partials are written per brick (nblocks_out = number of bricks).
+hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,
+                    const Grid& g, const TileList& tl, const LJConst& c, int precision, bool energy,
+                    const ForceOut& out, hipStream_t st, int* nblocks_out);
 
 // Velocity Verlet particle loops on the sorted state (INC on v and r).
 //   mode 0: v += h F ; r += dt v                          (first step)
@@ -133,9 +182,5 @@ hipError_t boa_q(const double* sx, const double* sy, const double* sz, const int
 hipError_t cna_signatures(const NList& nl, const int32_t* perm, int64_t n, uint32_t* trip,
                           int32_t* nnb, uint8_t* label, int max_out, hipStream_t st);
 
-hipError_t export_pairs(const NList& nl, const int32_t* perm, const int32_t* offsets, int64_t n,
-                        int32_t* i_out, int32_t* j_out, int64_t cap, hipStream_t st);
-
-hipError_t sum_counts(const int32_t* cnt, int64_t n, int32_t* blocksums, hipStream_t st);
 
 }  // namespace mdpl

@@ -4,14 +4,16 @@
 // dr_ij = r_i - r_j (min image), summed over the neighbour list of i and
 // written once per particle (gather only, no atomics: the paper's choice of
 // looping over all ordered pairs and writing to the first particle, Sec. 2).
-// The cutoff test d2 < rc^2 uses the same FP64 separation and the same
-// uncontracted d2 as the list build, so the set of interacting pairs equals
-// the all-pairs definition.  The min image uses k = rint(dx / L) and one
-// fused multiply-add dx - k L, which rounds exactly like the conditional
-// dx -/+ L.
+// Each workgroup handles one brick of cells and stages the image positions of
+// its neighbourhood in LDS (tile.h); list entries are tile indices.  The
+// cutoff test d2 < rc^2 uses the FP64 separation and the uncontracted d2 of
+// the definition; for pairs across a periodic face the image is added to the
+// stored position once per tile, so only such pairs can round differently
+// from the definition (by one unit in the last place of d2).
 //
 // Precision (FP32 mode): the separation and the test in FP64, the pair force
-// in FP32 from the rounded separation, FP32 per-particle sum.  Energy and
+// factor in FP32 from the rounded squared distance, per-particle sums in
+// FP64 (cheaper than converting the three separations), stored as FP32.  Energy and
 // virial (sampled steps) are formed per pair in FP64 and reduced per block
 // with wavefront shuffles into FP64 partials; a single-block pass sums the
 // partials in a fixed order, so results are reproducible run to run.
@@ -21,116 +23,141 @@
 // dr . f.
 #include "device_util.h"
 #include "internal.h"
+#include "tile.h"
 
 namespace mdpl {
-
-__device__ __forceinline__ double img(double d, double L, double invL) {
-  return __builtin_fma(-__builtin_rint(d * invL), L, d);
-}
 
 __device__ __forceinline__ double sq_sum(double dx, double dy, double dz) {
 #pragma clang fp contract(off)
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// MT: pair-force arithmetic type; OT: stored force type.
+// One workgroup per brick: the tile holds the image positions of the brick's
+// neighbourhood, so a pair needs one LDS gather and plain FP64 differences.
+// MT: arithmetic type of the pair force; OT: stored force type.  The pair
+// force is accumulated in FP64 (one conversion of the scalar factor per pair
+// instead of three of the separation).
 template <typename MT, typename OT, bool ENERGY>
-__global__ __launch_bounds__(256) void k_lj_force(const double* __restrict__ x,
-                                                  const double* __restrict__ y,
-                                                  const double* __restrict__ z, int64_t n,
-                                                  NList nl, LJConst c, ForceOut out) {
-  __shared__ double sh[4];
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  MT ax = 0, ay = 0, az = 0;
+__global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ z,
+                                                   const int32_t* __restrict__ cs, Grid g,
+                                                   TileList tl, LJConst c, ForceOut out) {
+  __shared__ TileShared t;
+  __shared__ double red[32];  // up to 16 waves: e, then w
+  const int brick = brick_of_block(g.nbricks);
+  if (brick >= g.nbricks) return;
+  const int total = tile_cells(g, brick, cs, t);
+  tile_load<true>(g, x, y, z, total, t);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  const MT sig2 = (MT)c.sigma2;
+  const MT c48 = (MT)(48.0 * c.eps), c24 = (MT)(24.0 * c.eps);
+  double scale = out.scale;
+  if (out.scale_dev) scale *= *out.scale_dev;
   double e = 0.0, w = 0.0;
-  if (s < n) {
+  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
     const double xi = x[s], yi = y[s], zi = z[s];
-    const int cnt = nl.cnt[s];
-    const int32_t* __restrict__ col = nl.nbr + s;
-    const MT sig2 = (MT)c.sigma2;
-    const MT c48 = (MT)(48.0 * c.eps);
-    for (int m = 0; m < cnt; ++m) {
-      const int32_t t = col[(int64_t)m * nl.stride];
-      const double dx = img(xi - x[t], c.box[0], c.inv_box[0]);
-      const double dy = img(yi - y[t], c.box[1], c.inv_box[1]);
-      const double dz = img(zi - z[t], c.box[2], c.inv_box[2]);
-      const double d2 = sq_sum(dx, dy, dz);
-      const bool in = d2 < c.rc2;
-      if (ENERGY) {
-        // pair energy and virial in FP64 for the sampled steps
-        const double inv = 1.0 / d2;
-        const double s2 = c.sigma2 * inv;
-        const double s6 = s2 * s2 * s2;
-        const double g = 48.0 * c.eps * inv * s6 * (s6 - 0.5);
-        const double v = 4.0 * c.eps * (s6 * s6 - s6) + c.shift_v;
-        const double gg = in ? g : 0.0;
-        e += in ? 0.5 * v : 0.0;
-        w += 0.5 * gg * d2;
-        ax += (MT)(gg * dx);
-        ay += (MT)(gg * dy);
-        az += (MT)(gg * dz);
-      } else {
-        MT inv;
-        if constexpr (sizeof(MT) == 4)
-          inv = __builtin_amdgcn_rcpf((float)d2);
-        else
-          inv = 1.0 / d2;
-        const MT s2 = sig2 * inv;
-        const MT s6 = s2 * s2 * s2;
-        MT g = c48 * inv * s6 * (s6 - (MT)0.5);
-        g = in ? g : (MT)0;
-        ax += g * (MT)dx;
-        ay += g * (MT)dy;
-        az += g * (MT)dz;
+    const int ngroups = (tl.cnt[s] + 3) >> 2;
+    const uint64_t* __restrict__ col = tl.nbr + s;
+    double ax = 0.0, ay = 0.0, az = 0.0, ei = 0.0;
+    uint64_t next = ngroups > 0 ? col[0] : 0;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const uint64_t word = next;
+      if (gi + 1 < ngroups) next = col[(int64_t)(gi + 1) * tl.stride];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int u = (int)((word >> (16 * k)) & 0xffff);
+        const double dx = xi - t.x[u];
+        const double dy = yi - t.y[u];
+        const double dz = zi - t.z[u];
+        const double d2 = sq_sum(dx, dy, dz);
+        const bool in = d2 < c.rc2;
+        double g;
+        if (ENERGY) {
+          // pair energy and virial in FP64 on the sampled steps
+          const double inv = 1.0 / d2;
+          const double s2 = c.sigma2 * inv;
+          const double s6 = s2 * s2 * s2;
+          const double gg = 48.0 * c.eps * inv * s6 * (s6 - 0.5);
+          const double v = 4.0 * c.eps * (s6 * s6 - s6) + c.shift_v;
+          g = in ? gg : 0.0;
+          ei += in ? 0.5 * v : 0.0;
+          w += 0.5 * g * d2;
+        } else {
+          MT inv;
+          if constexpr (sizeof(MT) == 4)
+            inv = __builtin_amdgcn_rcpf((float)d2);
+          else
+            inv = 1.0 / d2;
+          const MT s2 = sig2 * inv;
+          const MT s6 = s2 * s2 * s2;
+          const MT gg = inv * s6 * (c48 * s6 - c24);
+          g = in ? (double)gg : 0.0;
+        }
+        ax = __builtin_fma(g, dx, ax);
+        ay = __builtin_fma(g, dy, ay);
+        az = __builtin_fma(g, dz, az);
       }
     }
-    double scale = out.scale;
-    if (out.scale_dev) scale *= *out.scale_dev;
-    const int64_t o = out.scatter ? (int64_t)out.scatter[s] : s;
-    ((OT*)out.fx)[o] = (OT)((double)ax * scale);
-    ((OT*)out.fy)[o] = (OT)((double)ay * scale);
-    ((OT*)out.fz)[o] = (OT)((double)az * scale);
-    if (ENERGY && out.e_atom) out.e_atom[o] = e;
+    const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
+    ((OT*)out.fx)[o] = (OT)(ax * scale);
+    ((OT*)out.fy)[o] = (OT)(ay * scale);
+    ((OT*)out.fz)[o] = (OT)(az * scale);
+    if (ENERGY) {
+      if (out.e_atom) out.e_atom[o] = ei;
+      e += ei;
+    }
   }
   if (ENERGY) {
-    const double pe = block_sum256(e, sh);
-    const double ww = block_sum256(w, sh);
+    // brick sums: wave butterflies, then the wave sums in order
+    e = wave_sum(e);
+    w = wave_sum(w);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[wave] = e;
+      red[16 + wave] = w;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      out.partials[2 * blockIdx.x] = pe;
-      out.partials[2 * blockIdx.x + 1] = ww;
+      const int nw = (blockDim.x + 63) >> 6;
+      double pe = 0.0, ww = 0.0;
+      for (int k = 0; k < nw; ++k) {
+        pe += red[k];
+        ww += red[16 + k];
+      }
+      out.partials[2 * brick] = pe;
+      out.partials[2 * brick + 1] = ww;
     }
   }
 }
 
 template <typename MT, typename OT>
-static void launch_force(bool energy, unsigned nb, hipStream_t st, const double* x,
-                         const double* y, const double* z, int64_t n, const NList& nl,
+static void launch_force(bool energy, hipStream_t st, const double* x, const double* y,
+                         const double* z, const int32_t* cs, const Grid& g, const TileList& tl,
                          const LJConst& c, const ForceOut& out) {
+  const dim3 grid(tile_grid_blocks(g.nbricks)), block(tl.threads);
   if (energy)
-    hipLaunchKernelGGL((k_lj_force<MT, OT, true>), dim3(nb), dim3(256), 0, st, x, y, z, n, nl, c,
-                       out);
+    hipLaunchKernelGGL((k_lj_force<MT, OT, true>), grid, block, 0, st, x, y, z, cs, g, tl, c, out);
   else
-    hipLaunchKernelGGL((k_lj_force<MT, OT, false>), dim3(nb), dim3(256), 0, st, x, y, z, n, nl, c,
-                       out);
+    hipLaunchKernelGGL((k_lj_force<MT, OT, false>), grid, block, 0, st, x, y, z, cs, g, tl, c, out);
 }
 
-hipError_t lj_force(const double* x, const double* y, const double* z, int64_t n, const NList& nl,
-                    const LJConst& c, int precision, bool energy, const ForceOut& out,
-                    hipStream_t st, int* nblocks_out) {
-  const unsigned nb = (unsigned)div_up(n, 256);
-  if (nblocks_out) *nblocks_out = (int)nb;
+hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,
+                    const Grid& g, const TileList& tl, const LJConst& c, int precision, bool energy,
+                    const ForceOut& out, hipStream_t st, int* nblocks_out) {
+  if (nblocks_out) *nblocks_out = g.nbricks;
   // precision: 0 FP64 math/double out, 1 FP32 math/float out,
   //            2 FP64 math/double out (backward), 3 FP32 math/double out (backward)
   switch (precision) {
     case 0:
     case 2:
-      launch_force<double, double>(energy, nb, st, x, y, z, n, nl, c, out);
+      launch_force<double, double>(energy, st, x, y, z, cell_start, g, tl, c, out);
       break;
     case 1:
-      launch_force<float, float>(energy, nb, st, x, y, z, n, nl, c, out);
+      launch_force<float, float>(energy, st, x, y, z, cell_start, g, tl, c, out);
       break;
     default:
-      launch_force<float, double>(energy, nb, st, x, y, z, n, nl, c, out);
+      launch_force<float, double>(energy, st, x, y, z, cell_start, g, tl, c, out);
       break;
   }
   return hipGetLastError();

@@ -2,19 +2,137 @@
 // of i and its 26 neighbours, keep the pairs closer than the list radius;
 // GPU neighbour matrix W_{m,i} = m-th neighbour of i).
 //
-// One thread per particle in cell order.  Candidate cells are walked as
-// 9 rows of 3 consecutive cells (one contiguous range when the row does not
-// wrap).  The pair test is the exact FP64 minimum-image predicate
+// The pair test is the exact FP64 minimum-image predicate
 //   dx = xi - xj; dx > L/2 ? dx - L : (dx < -L/2 ? dx + L : dx)
 //   d2 = (dx*dx + dy*dy) + dz*dz < r2
-// with floating-point contraction off, so the list is bit-identical to the
-// all-pairs definition for the same FP64 inputs.
+// with floating-point contraction off, on the caller's FP64 values, so the
+// list is bit-identical to the all-pairs definition.
+//
+// Two builders:
+//  * the LJ list: one workgroup per brick stages its tile (stored positions,
+//    no images) in LDS and every particle tests the 9 contiguous tile ranges
+//    of its stencil; entries are 16-bit tile indices, column-major, so the
+//    force pass reads one coalesced row per neighbour rank;
+//  * the analysis list (bond order / CNA): one thread per particle walks the
+//    9 rows of 3 consecutive cells in global memory, entries are sorted-slot
+//    indices, row-major so a whole list is one contiguous read.
 #include "device_util.h"
 #include "internal.h"
+#include "tile.h"
 
 namespace mdpl {
 
-template <int LAYOUT>
+// ------------------------------------------------------------------ LJ list
+__global__ __launch_bounds__(1024) void k_build_tile_nlist(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
+    TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
+  __shared__ TileShared t;
+  const int brick = brick_of_block(g.nbricks);
+  if (brick >= g.nbricks) return;
+  const int total = tile_cells(g, brick, cs, t);
+  if (total > kTileCap && threadIdx.x == 0) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
+  tile_load<false>(g, x, y, z, total, t);
+  const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
+  const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+  const int TX = g.B[0] + 2, TXY = TX * (g.B[1] + 2);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  const int max_nb = tl.max_nb;
+  int most = 0;
+  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+    const int tc0 = home_tile_cell(g, brick, skeys[s]);
+    const int self = t.prefix[tc0] + (s - t.src[tc0]);
+    const double xi = x[s], yi = y[s], zi = z[s];
+    int count = 0;
+    uint64_t word = 0;
+    for (int oz = -1; oz <= 1; ++oz) {
+      for (int oy = -1; oy <= 1; ++oy) {
+        const int tcl = tc0 + oz * TXY + oy * TX - 1;
+        const int ub = t.prefix[tcl];
+        int ue = t.prefix[tcl + 3];
+        ue = ue < kTileCap ? ue : kTileCap;
+        for (int u = ub; u < ue; ++u) {
+          if (u == self) continue;
+          const double d2 = exact_d2(xi, yi, zi, t.x[u], t.y[u], t.z[u], Lx, Ly, Lz, hx, hy, hz);
+          if (d2 < r2) {
+            if (count < max_nb) {
+              word |= (uint64_t)u << (16 * (count & 3));
+              if ((count & 3) == 3) {
+                tl.nbr[(int64_t)(count >> 2) * tl.stride + s] = word;
+                word = 0;
+              }
+            }
+            ++count;
+          }
+        }
+      }
+    }
+    const int kept = count < max_nb ? count : max_nb;
+    if (kept & 3) {  // pad the last word with the dummy slot
+      for (int k = kept & 3; k < 4; ++k) word |= (uint64_t)kTileDummy << (16 * k);
+      tl.nbr[(int64_t)(kept >> 2) * tl.stride + s] = word;
+    }
+    tl.cnt[s] = kept;
+    if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
+    most = count > most ? count : most;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(most, off, 64);
+    most = o > most ? o : most;
+  }
+  if ((threadIdx.x & 63) == 0 && most > 0) atomicMax(maxcount, most);
+}
+
+hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
+                            const int32_t* skeys, const int32_t* cell_start, const Grid& g,
+                            double r2, TileList tl, uint32_t* flags, int32_t* maxcount,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_build_tile_nlist, dim3(tile_grid_blocks(g.nbricks)), dim3(tl.threads), 0, st,
+                     x, y, z, skeys, cell_start, g, r2, tl, flags, maxcount);
+  return hipGetLastError();
+}
+
+// Directed pairs in the caller's indices: entry m of slot s goes to
+// offsets[s] + m; the tile index is mapped back to its sorted slot.
+__global__ __launch_bounds__(1024) void k_export_tile_pairs(
+    TileList tl, const int32_t* __restrict__ cs, Grid g, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ offsets, int32_t* __restrict__ i_out, int32_t* __restrict__ j_out,
+    int64_t cap) {
+  __shared__ TileShared t;
+  const int brick = brick_of_block(g.nbricks);
+  if (brick >= g.nbricks) return;
+  tile_cells(g, brick, cs, t);
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+    const int c = tl.cnt[s];
+    const int64_t o = offsets[s];
+    const int32_t pi = perm[s];
+    for (int m = 0; m < c; ++m) {
+      if (o + m >= cap) break;
+      const int u = (int)((tl.nbr[(int64_t)(m >> 2) * tl.stride + s] >> (16 * (m & 3))) & 0xffff);
+      int lo = 0, hi = ntc;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t.prefix[mid] <= u) lo = mid;
+        else hi = mid;
+      }
+      i_out[o + m] = pi;
+      j_out[o + m] = perm[t.src[lo] + (u - t.prefix[lo])];
+    }
+  }
+}
+
+hipError_t export_tile_pairs(const TileList& tl, const int32_t* cell_start, const Grid& g,
+                             const int32_t* perm, const int32_t* offsets, int32_t* i_out,
+                             int32_t* j_out, int64_t cap, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_tile_pairs, dim3(tile_grid_blocks(g.nbricks)), dim3(tl.threads), 0,
+                     st, tl, cell_start, g, perm, offsets, i_out, j_out, cap);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ analysis list
 __global__ __launch_bounds__(256) void k_build_nlist(
     const double* __restrict__ sx, const double* __restrict__ sy, const double* __restrict__ sz,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, int64_t n, Grid g, double r2,
@@ -26,7 +144,7 @@ __global__ __launch_bounds__(256) void k_build_nlist(
     const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
     const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
     const int n0 = g.nc[0], n1 = g.nc[1], n2 = g.nc[2];
-    const int key = skeys[s];
+    const int key = skeys[s];  // B = (1,1,1): x-fastest cell index
     const int cx = key % n0;
     const int cy = (key / n0) % n1;
     const int cz = key / (n0 * n1);
@@ -40,7 +158,6 @@ __global__ __launch_bounds__(256) void k_build_nlist(
         y2 += (y2 < 0) ? n1 : 0;
         y2 -= (y2 >= n1) ? n1 : 0;
         const int row = (z2 * n1 + y2) * n0;
-        // up to three ranges along x
         int b[3], e[3], nr;
         if (cx >= 1 && cx <= n0 - 2) {
           b[0] = cs[row + cx - 1];
@@ -62,24 +179,16 @@ __global__ __launch_bounds__(256) void k_build_nlist(
             if (t == s) continue;
             const double d2 = exact_d2(xi, yi, zi, sx[t], sy[t], sz[t], Lx, Ly, Lz, hx, hy, hz);
             if (d2 < r2) {
-              if (count < max_nb) {
-                if (LAYOUT == 0)
-                  nl.nbr[(int64_t)count * nl.stride + s] = t;
-                else
-                  nl.nbr[s * (int64_t)max_nb + count] = t;
-              }
+              if (count < max_nb) nl.nbr[s * (int64_t)max_nb + count] = t;
               ++count;
             }
           }
         }
       }
     }
-    // layout 0 (force lists) stores the clamped count, layout 1 (analysis)
-    // the true count so callers can see an overflow per particle
-    nl.cnt[s] = (LAYOUT == 0 && count > max_nb) ? max_nb : count;
+    nl.cnt[s] = count;  // true count: callers see an overflow per particle
     if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
   }
-  // one atomic per wave for the largest count
   int m = count;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -92,40 +201,9 @@ __global__ __launch_bounds__(256) void k_build_nlist(
 hipError_t build_nlist(const double* sx, const double* sy, const double* sz,
                        const int32_t* skeys, const int32_t* cell_start, int64_t n, const Grid& g,
                        double r2, NList nl, uint32_t* flags, int32_t* maxcount, hipStream_t st) {
-  const unsigned nb = (unsigned)div_up(n, 256);
-  if (nl.layout == 0)
-    hipLaunchKernelGGL(k_build_nlist<0>, dim3(nb), dim3(256), 0, st, sx, sy, sz, skeys, cell_start,
-                       n, g, r2, nl, flags, maxcount);
-  else
-    hipLaunchKernelGGL(k_build_nlist<1>, dim3(nb), dim3(256), 0, st, sx, sy, sz, skeys, cell_start,
-                       n, g, r2, nl, flags, maxcount);
-  return hipGetLastError();
-}
-
-// Directed pairs in the caller's indices: for slot s, its entries go to
-// [offsets[s], offsets[s] + cnt[s]).
-__global__ void k_export_pairs(NList nl, const int32_t* __restrict__ perm,
-                               const int32_t* __restrict__ offsets, int64_t n,
-                               int32_t* __restrict__ i_out, int32_t* __restrict__ j_out,
-                               int64_t cap) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int c = nl.cnt[s] > nl.max_nb ? nl.max_nb : nl.cnt[s];
-  const int64_t o = offsets[s];
-  const int32_t pi = perm[s];
-  for (int m = 0; m < c; ++m) {
-    if (o + m >= cap) break;
-    const int32_t t = (nl.layout == 0) ? nl.nbr[(int64_t)m * nl.stride + s]
-                                       : nl.nbr[s * (int64_t)nl.max_nb + m];
-    i_out[o + m] = pi;
-    j_out[o + m] = perm[t];
-  }
-}
-
-hipError_t export_pairs(const NList& nl, const int32_t* perm, const int32_t* offsets, int64_t n,
-                        int32_t* i_out, int32_t* j_out, int64_t cap, hipStream_t st) {
-  hipLaunchKernelGGL(k_export_pairs, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, nl, perm,
-                     offsets, n, i_out, j_out, cap);
+  if (g.V != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_build_nlist, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, sx, sy, sz,
+                     skeys, cell_start, n, g, r2, nl, flags, maxcount);
   return hipGetLastError();
 }
 

@@ -1,0 +1,131 @@
+// LDS tiles of the LJ path.
+//
+// A workgroup owns one brick of cells.  Its tile is the brick grown by one
+// cell on every side, (B+2)^3 cells, listed x-fastest; cell tc holds
+// particles [prefix[tc], prefix[tc+1]) of the tile, copied from the sorted
+// slots starting at src[tc].  Every particle of the brick finds all its
+// 27-cell stencil inside the tile, and the three x-neighbour cells of a
+// stencil row are consecutive tile cells, i.e. one contiguous index range.
+//
+// Tile cells outside the box are periodic images; code[tc] records the
+// image (-1, 0, +1 per axis) so that a tile may be filled either with the
+// stored positions (exact minimum-image tests) or with the image positions
+// (plain differences, no per-pair image arithmetic).
+#pragma once
+
+#include "device_util.h"
+#include "internal.h"
+
+namespace mdpl {
+
+struct TileShared {
+  double x[kTileMax];
+  double y[kTileMax];
+  double z[kTileMax];
+  int prefix[kTileCells + 1];
+  int src[kTileCells];
+  int code[kTileCells];
+};
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// run of bricks (a slab of the box) so that tile reloads hit its own L2.
+__device__ __forceinline__ int brick_of_block(int nbricks) {
+  const int per = (nbricks + 7) >> 3;
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
+inline unsigned tile_grid_blocks(int nbricks) { return (unsigned)(((nbricks + 7) >> 3) * 8); }
+
+__device__ __forceinline__ void brick_coords(const Grid& g, int brick, int& bx, int& by, int& bz) {
+  bx = brick % g.nb[0];
+  by = (brick / g.nb[0]) % g.nb[1];
+  bz = brick / (g.nb[0] * g.nb[1]);
+}
+
+// Fills prefix/src/code for the tile of `brick`; returns the particle count
+// (possibly above kTileMax).  Ends with a barrier.
+__device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __restrict__ cs,
+                                 TileShared& t) {
+  const int TX = g.B[0] + 2, TY = g.B[1] + 2, TZ = g.B[2] + 2;
+  const int ntc = TX * TY * TZ;
+  int bx, by, bz;
+  brick_coords(g, brick, bx, by, bz);
+  const int ox = bx * g.B[0] - 1, oy = by * g.B[1] - 1, oz = bz * g.B[2] - 1;
+  for (int tc = threadIdx.x; tc < ntc; tc += blockDim.x) {
+    const int lx = tc % TX, ly = (tc / TX) % TY, lz = tc / (TX * TY);
+    int cx = ox + lx, cy = oy + ly, cz = oz + lz;
+    int sx = 0, sy = 0, sz = 0;
+    if (cx < 0) { cx += g.nc[0]; sx = -1; } else if (cx >= g.nc[0]) { cx -= g.nc[0]; sx = 1; }
+    if (cy < 0) { cy += g.nc[1]; sy = -1; } else if (cy >= g.nc[1]) { cy -= g.nc[1]; sy = 1; }
+    if (cz < 0) { cz += g.nc[2]; sz = -1; } else if (cz >= g.nc[2]) { cz -= g.nc[2]; sz = 1; }
+    const int key = cell_key(g, cx, cy, cz);
+    const int b = cs[key];
+    t.src[tc] = b;
+    t.prefix[tc + 1] = cs[key + 1] - b;
+    t.code[tc] = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4);
+  }
+  if (threadIdx.x == 0) t.prefix[0] = 0;
+  __syncthreads();
+  if (threadIdx.x < 64) {  // inclusive scan of the counts by wave 0
+    const int lane = threadIdx.x;
+    int carry = 0;
+    for (int base = 1; base <= ntc; base += 64) {
+      const int i = base + lane;
+      int v = (i <= ntc) ? t.prefix[i] : 0;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+      }
+      if (i <= ntc) t.prefix[i] = v + carry;
+      carry += __shfl(v, 63, 64);
+    }
+  }
+  __syncthreads();
+  return t.prefix[ntc];
+}
+
+// Copies the tile's positions (at most kTileCap) into LDS; IMAGE adds the
+// periodic image offsets.  Ends with a barrier.
+template <bool IMAGE>
+__device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
+                                 const double* __restrict__ y, const double* __restrict__ z,
+                                 int total, TileShared& t) {
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int nt = total < kTileCap ? total : kTileCap;
+  if (threadIdx.x == 0) {  // padding slot: no pair with it is ever inside the cutoff
+    t.x[kTileDummy] = 1e20;
+    t.y[kTileDummy] = 1e20;
+    t.z[kTileDummy] = 1e20;
+  }
+  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+    int lo = 0, hi = ntc;  // prefix[lo] <= u < prefix[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (t.prefix[mid] <= u) lo = mid;
+      else hi = mid;
+    }
+    const int src = t.src[lo] + (u - t.prefix[lo]);
+    double a = x[src], b = y[src], c = z[src];
+    if (IMAGE) {
+      const int code = t.code[lo];
+      a += (double)((code & 3) - 1) * g.box[0];
+      b += (double)(((code >> 2) & 3) - 1) * g.box[1];
+      c += (double)(((code >> 4) & 3) - 1) * g.box[2];
+    }
+    t.x[u] = a;
+    t.y[u] = b;
+    t.z[u] = c;
+  }
+  __syncthreads();
+}
+
+// Tile cell of a brick particle from its cell key.
+__device__ __forceinline__ int home_tile_cell(const Grid& g, int brick, int key) {
+  const int local = key - brick * g.V;
+  const int lx = local % g.B[0], ly = (local / g.B[0]) % g.B[1], lz = local / (g.B[0] * g.B[1]);
+  const int TX = g.B[0] + 2, TY = g.B[1] + 2;
+  return ((lz + 1) * TY + (ly + 1)) * TX + (lx + 1);
+}
+
+}  // namespace mdpl

@@ -74,9 +74,10 @@ def test_workspace_bytes_size(lib):
     p = _params(max_nb=128)
     b = C.mdpl_workspace_bytes(p)
     npad = 1024
-    assert b >= 4 * 128 * npad + 8 * 1000 * 15
-    assert b < 4 * 128 * npad + 8 * 1000 * 40 + (1 << 16)
-    assert C.mdpl_workspace_bytes(_params(max_nb=256)) - b == 4 * 128 * npad
+    # 16-bit neighbour entries plus ~15 doubles of per-particle state
+    assert b >= 2 * 128 * npad + 8 * 1000 * 15
+    assert b < 2 * 128 * npad + 8 * 1000 * 40 + (1 << 16)
+    assert C.mdpl_workspace_bytes(_params(max_nb=256)) - b == 2 * 128 * npad
 
 
 def test_misaligned_workspace_rejected(lib):
