@@ -165,10 +165,12 @@ def kinetic_energy(vel, mass: float = 1.0) -> float:
 
 
 def wrap(pos, box):
-    """Fold positions into [0, L) per axis."""
+    """Fold positions into [0, L) per axis: x - L floor(x / L), then one
+    correction by L if rounding left the value at L or below 0."""
     box = np.asarray(box, dtype=np.float64)
     p = pos - box[None, :] * np.floor(pos / box[None, :])
     p = np.where(p >= box[None, :], p - box[None, :], p)
+    p = np.where(p < 0.0, p + box[None, :], p)
     return p
 
 
