@@ -108,11 +108,12 @@ mdpl_status mdpl_sim_destroy(mdpl_sim* sim);
 
 /* Cell binning and neighbour-list construction for the given positions
  * (Sec. 3.1: cells of side >= rc+skin, 27-cell stencil, list of every j != i
- * with |r_i - r_j| < rc+skin under the minimum image).  Particles are
- * counting-sorted by cell into workspace copies; the caller's arrays are not
- * modified.  Positions should lie in [0, L); any value with
- * -L/4 <= x < 5L/4 gives the same list as its folded image would under the
- * minimum-image rule. */
+ * with |r_i - r_j| < rc+skin under the minimum image).  Positions are first
+ * folded into the box, x - L floor(x / L) (then x - L if that rounds to L),
+ * and the list is that of the folded positions, tested exactly as
+ * (dx*dx + dy*dy) + dz*dz < (rc+skin)^2 in double with the conditional
+ * minimum image dx -/+ L.  Particles are counting-sorted by cell into
+ * workspace copies; the caller's arrays are not modified. */
 mdpl_status mdpl_build(mdpl_sim* sim, const double* x, const double* y, const double* z);
 
 /* Copy the list of the last mdpl_build as directed pairs (i, j) in the

@@ -106,7 +106,7 @@ mdpl_status validate(const mdpl_lj_params* p) {
 
 // Brick of cells handled by one workgroup of the LJ kernels: the largest
 // cube (3, 2 or 1 cells) whose tile, (B+2)^3 cells at the mean occupancy,
-// fills at most 80% of the LDS tile; workgroup size ~1.15x its particles.
+// fills at most 85% of the LDS tile; workgroup size ~1.15x its particles.
 void lj_grid(const mdpl_lj_params* p, Grid* g, int* threads) {
   int unit[3] = {1, 1, 1};
   make_grid(p->box, p->rc + p->skin, unit, g);
@@ -114,7 +114,7 @@ void lj_grid(const mdpl_lj_params* p, Grid* g, int* threads) {
   int b = 1;
   for (int cand = 3; cand >= 1; --cand) {
     const double tile = (cand + 2.0) * (cand + 2.0) * (cand + 2.0) * per_cell;
-    if (tile <= 0.8 * kTileMax) {
+    if (tile <= 0.85 * kTileMax) {
       b = cand;
       break;
     }
@@ -297,7 +297,7 @@ mdpl_status mdpl_build(mdpl_sim* s, const double* x, const double* y, const doub
   HIP_TRY(bin_particles(x, y, z, s->n, s->g, s->sort, s->cell_start, &skeys, &svals, s->st));
   HIP_TRY(hipMemcpyAsync(s->perm, svals, 4 * (size_t)s->n, hipMemcpyDeviceToDevice, s->st));
   s->skeys = skeys;
-  HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, false, s->st));
+  HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, true, s->st));
   HIP_TRY(build_tile_nlist(s->sx, s->sy, s->sz, skeys, s->cell_start, s->g, s->r2ext, s->tl,
                            s->flags, s->maxcount, s->st));
   s->built = true;

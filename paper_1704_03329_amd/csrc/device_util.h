@@ -5,8 +5,10 @@
 
 namespace mdpl {
 
-// Fold a coordinate into [0, L).
+// Fold a coordinate into [0, L): x - L floor(x / L), each operation rounded
+// (no contraction), then one correction step against rounding to L.
 __device__ __forceinline__ double fold(double x, double L) {
+#pragma clang fp contract(off)
   double w = x - L * floor(x / L);
   if (w >= L) w -= L;
   if (w < 0.0) w += L;

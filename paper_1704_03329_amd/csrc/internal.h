@@ -113,7 +113,8 @@ hipError_t build_nlist(const double* sx, const double* sy, const double* sz,
 // words column-major: entry m of slot s is 16-bit lane (m & 3) of
 // nbr[(m >> 2) * stride + s].  The last word of a list is padded with
 // kTileDummy, a tile slot that holds a position far outside the box.
-constexpr int kTileMax = 3200;              // tile slots (LDS)
+constexpr int kTileMax = 3072;              // tile slots (LDS)
+constexpr int kBrickMax = 1024;             // particles of one brick the list builder counts
 constexpr int kTileDummy = kTileMax - 1;    // padding slot
 constexpr int kTileCap = kTileMax - 1;      // particles a tile can hold
 constexpr int kTileCells = 125;             // B <= 3 per axis

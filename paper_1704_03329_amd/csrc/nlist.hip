@@ -10,9 +10,9 @@
 //
 // Two builders:
 //  * the LJ list: one workgroup per brick stages its tile (stored positions,
-//    no images) in LDS and every particle tests the 9 contiguous tile ranges
-//    of its stencil; entries are 16-bit tile indices, column-major, so the
-//    force pass reads one coalesced row per neighbour rank;
+//    no images) in LDS, one wave per home cell tests the 27 tile cells of its
+//    stencil; entries are 16-bit tile indices, column-major, so the force
+//    pass reads one coalesced word per four neighbours;
 //  * the analysis list (bond order / CNA): one thread per particle walks the
 //    9 rows of 3 consecutive cells in global memory, entries are sorted-slot
 //    indices, row-major so a whole list is one contiguous read.
@@ -23,55 +23,97 @@
 namespace mdpl {
 
 // ------------------------------------------------------------------ LJ list
+// One wave per home cell at a time.  The cell's particles (na <= 64 per
+// pass) are spread over the 64 lanes as na x K (K = 64 / na): lane
+// (a, k) tests particle a against candidates k, k+K, k+2K, ... of every
+// stencil cell, so all lanes walk the same 27 cells together and lanes with
+// equal k read the same tile slot.  Accepted neighbours get their rank from
+// a per-particle LDS counter and are stored as 16-bit halves of the list
+// words; a final pass pads the last word and writes the counts.
+//
+// Cells without a periodic image (code 0) use the stored positions directly,
+// which is exactly the definition's arithmetic; image cells fall back to the
+// exact conditional minimum image.
 __global__ __launch_bounds__(1024) void k_build_tile_nlist(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
     TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
   __shared__ TileShared t;
+  __shared__ int acnt[kBrickMax];
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
-  if (total > kTileCap && threadIdx.x == 0) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
-  tile_load<false>(g, x, y, z, total, t);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  const int nbrick = s1 - s0;
+  if (threadIdx.x == 0 && (total > kTileCap || nbrick > kBrickMax))
+    atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
+  for (int a = threadIdx.x; a < kBrickMax; a += blockDim.x) acnt[a] = 0;
+  tile_load<false>(g, x, y, z, total, t);  // ends with a barrier
   const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
   const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
   const int TX = g.B[0] + 2, TXY = TX * (g.B[1] + 2);
-  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const int max_nb = tl.max_nb;
-  int most = 0;
-  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
-    const int tc0 = home_tile_cell(g, brick, skeys[s]);
-    const int self = t.prefix[tc0] + (s - t.src[tc0]);
-    const double xi = x[s], yi = y[s], zi = z[s];
-    int count = 0;
-    uint64_t word = 0;
-    for (int oz = -1; oz <= 1; ++oz) {
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int tcl = tc0 + oz * TXY + oy * TX - 1;
-        const int ub = t.prefix[tcl];
-        int ue = t.prefix[tcl + 3];
-        ue = ue < kTileCap ? ue : kTileCap;
-        for (int u = ub; u < ue; ++u) {
-          if (u == self) continue;
-          const double d2 = exact_d2(xi, yi, zi, t.x[u], t.y[u], t.z[u], Lx, Ly, Lz, hx, hy, hz);
-          if (d2 < r2) {
-            if (count < max_nb) {
-              word |= (uint64_t)u << (16 * (count & 3));
-              if ((count & 3) == 3) {
-                tl.nbr[(int64_t)(count >> 2) * tl.stride + s] = word;
-                word = 0;
+  uint16_t* __restrict__ half = (uint16_t*)tl.nbr;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  int bx, by, bz;
+  brick_coords(g, brick, bx, by, bz);
+  for (int lc = wave; lc < g.V; lc += nwaves) {
+    const int lx = lc % g.B[0], ly = (lc / g.B[0]) % g.B[1], lz = lc / (g.B[0] * g.B[1]);
+    // the last brick along an axis may be partial: its missing cells would
+    // alias periodic images of another brick's cells
+    if (bx * g.B[0] + lx >= g.nc[0] || by * g.B[1] + ly >= g.nc[1] || bz * g.B[2] + lz >= g.nc[2])
+      continue;
+    const int tc0 = ((lz + 1) * (g.B[1] + 2) + (ly + 1)) * TX + (lx + 1);
+    const int ncell = t.prefix[tc0 + 1] - t.prefix[tc0];
+    const int slot0 = t.src[tc0];
+    for (int a0 = 0; a0 < ncell; a0 += 64) {
+      const int na = ncell - a0 < 64 ? ncell - a0 : 64;
+      const int K = 64 / na;
+      const int a = a0 + lane % na, k = lane / na;
+      const bool active = k < K;
+      const int self = t.prefix[tc0] + a;
+      const int s = slot0 + a;          // sorted slot of particle a
+      const int la = s - s0;            // its index within the brick
+      const bool ok = active && self < kTileCap && la >= 0 && la < kBrickMax && s < s1;
+      const double xi = ok ? t.x[self] : 0.0, yi = ok ? t.y[self] : 0.0, zi = ok ? t.z[self] : 0.0;
+      for (int oz = -1; oz <= 1; ++oz) {
+        for (int oy = -1; oy <= 1; ++oy) {
+          const int tcl = tc0 + oz * TXY + oy * TX - 1;
+          for (int tc = tcl; tc < tcl + 3; ++tc) {
+            const int code = t.code[tc];
+            int ue = t.prefix[tc + 1];
+            ue = ue < kTileCap ? ue : kTileCap;
+            const int ub = t.prefix[tc] + k;
+            if (!ok) continue;
+            for (int u = ub; u < ue; u += K) {
+              double d2;
+              if (code == 21) {  // no image: (1,1,1) in the 2-bit fields
+#pragma clang fp contract(off)
+                const double dx = xi - t.x[u], dy = yi - t.y[u], dz = zi - t.z[u];
+                d2 = (dx * dx + dy * dy) + dz * dz;
+              } else {
+                d2 = exact_d2(xi, yi, zi, t.x[u], t.y[u], t.z[u], Lx, Ly, Lz, hx, hy, hz);
+              }
+              if (d2 < r2 && u != self) {
+                const int m = atomicAdd(&acnt[la], 1);
+                if (m < max_nb) half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)u;
               }
             }
-            ++count;
           }
         }
       }
     }
+  }
+  __syncthreads();
+  int most = 0;
+  const int nb = nbrick < kBrickMax ? nbrick : kBrickMax;
+  for (int la = threadIdx.x; la < nb; la += blockDim.x) {
+    const int s = s0 + la;
+    const int count = acnt[la];
     const int kept = count < max_nb ? count : max_nb;
-    if (kept & 3) {  // pad the last word with the dummy slot
-      for (int k = kept & 3; k < 4; ++k) word |= (uint64_t)kTileDummy << (16 * k);
-      tl.nbr[(int64_t)(kept >> 2) * tl.stride + s] = word;
-    }
+    for (int m = kept; m < ((kept + 3) & ~3); ++m)  // pad the last word
+      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)kTileDummy;
     tl.cnt[s] = kept;
     if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
     most = count > most ? count : most;
