@@ -82,6 +82,121 @@ def cpu_baseline(pos, box, rows: int):
     }
 
 
+def event_time(fn, reps: int) -> float:
+    """Average seconds of fn() over reps calls, timed with events on the
+    current stream (every call of the path enqueues on it)."""
+    import torch
+
+    fn()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
+def mlp_report(args):
+    """The learned potential beside plain LJ: train on engine-generated
+    snapshots, then time one force evaluation of each on the evaluation
+    configuration and state the MLP's force error against FP64 LJ."""
+    import numpy as np
+    import torch
+
+    import mdinputs
+    from paper_1704_03329_amd import potential as P
+    from paper_1704_03329_amd.sim import LJSim, soa
+
+    t0 = time.perf_counter()
+    log("MLP: generating 200 training snapshots (FCC 10^3, N=4000, T* 0.7/1.0/1.5)")
+    data = P.generate_training_set()
+    snap = data["snap"].cpu().numpy()
+    temp = data["temp"].cpu().numpy()
+    # 20 validation snapshots, stratified by temperature: the last ones of each T*
+    val_snaps = []
+    for T in (0.7, 1.0, 1.5):
+        s_t = np.unique(snap[np.isclose(temp, T)])
+        val_snaps.extend(s_t[-(7 if T < 1.4 else 6):].tolist())
+    is_val = np.isin(snap, val_snaps)
+    tr = torch.from_numpy(np.nonzero(~is_val)[0]).cuda()
+    va = torch.from_numpy(np.nonzero(is_val)[0]).cuda()
+    Gtr, etr = data["G"][tr].contiguous(), data["e"][tr].contiguous()
+    Gva, eva = data["G"][va].contiguous(), data["e"][va].contiguous()
+    model = P.MLPPotential(seed=11)
+    model.set_standardisation(Gtr, etr)
+    e0, _ = model.energy(Gva)
+    mae_untrained = float(torch.mean(torch.abs(e0.double() - eva)).item())
+    log(f"MLP: training {args.mlp_steps} Adam steps, batch 4096, on {tr.numel()} atoms")
+    t_train = time.perf_counter()
+    losses = model.train(Gtr, etr, steps=args.mlp_steps, batch=4096, lr=3e-3, lr_final=1e-4,
+                         log_every=max(args.mlp_steps // 4, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    e1, _ = model.energy(Gva)
+    mae_val = float(torch.mean(torch.abs(e1.double() - eva)).item())
+
+    log("MLP: evaluation configuration (64^3 sc, rho 0.8442, melted 2000 steps at T*=1, seed 43)")
+    d = mdinputs.lj_fluid(64, temperature=1.0, seed=43)
+    n = d["pos"].shape[0]
+    box = d["box"]
+    md = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp64", shift="cutoff")
+    st = md.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    md.run(st, 2000, 0)
+    md.check()
+    pos = torch.stack([st["x"], st["y"], st["z"]], 1)
+    x, y, z = soa(pos)
+    ref = LJSim(n, box, rc=2.5, skin=0.3, precision="fp64", shift="none")
+    ref.build(x, y, z)
+    fx, fy, fz, _, e_lj = ref.forces(x, y, z, energy=True, per_atom=True)
+    F_lj = torch.stack([fx, fy, fz], 1)
+    lj32 = LJSim(n, box, rc=2.5, skin=0.3, precision="fp32", shift="none")
+    lj32.build(x, y, z)
+    f32 = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+
+    def lj_force():
+        lj32_forces(lj32, x, y, z, f32)
+
+    lj_force()
+    buf = model.buffers(n)
+    model.forces(ref, x, y, z, buf)
+    F_mlp = torch.stack([buf["fx"], buf["fy"], buf["fz"]], 1).double()
+    e_mlp = buf["e"].double()
+    F32 = torch.stack(f32, 1).double()
+    rms = lambda t: float(torch.sqrt(torch.mean(t * t)).item())  # noqa: E731
+    reps = 50
+    t_lj = event_time(lj_force, reps)
+    t_mlp = event_time(lambda: model.forces(ref, x, y, z, buf), reps)
+    t_build = event_time(lambda: ref.build(x, y, z), 10)
+    log(f"MLP: LJ force {t_lj * 1e6:.1f} us, MLP energy+forces {t_mlp * 1e6:.1f} us, build {t_build * 1e6:.1f} us")
+    return {
+        "workload": f"MLP 24-64-64-1 (16 radial + 8 angular features within 2.5, BF16 weights, FP32 "
+                    f"accumulation) vs LJ forces on N={n} (64^3 sc melted 2000 steps at T*=1, seed 43); "
+                    "trained on 180 + 20 validation snapshots of N=4000 at T* 0.7/1.0/1.5",
+        "n_atoms": n,
+        "mlp_us_per_eval": t_mlp * 1e6,
+        "lj_fp32_us_per_eval": t_lj * 1e6,
+        "nlist_build_us": t_build * 1e6,
+        "time_ratio_mlp_over_lj": t_mlp / t_lj,
+        "mlp_force_rmse": rms(F_mlp - F_lj),
+        "lj_fp32_force_rmse": rms(F32 - F_lj),
+        "lj_force_rms": rms(F_lj),
+        "mlp_energy_mae_per_atom": float(torch.mean(torch.abs(e_mlp - e_lj)).item()),
+        "validation_energy_mae": {"trained": mae_val, "untrained": mae_untrained},
+        "train_steps": args.mlp_steps,
+        "train_seconds": t_train,
+        "train_loss_first_last": [losses[0][1], losses[-1][1]],
+        "seconds_total": time.perf_counter() - t0,
+    }
+
+
+def lj32_forces(sim, x, y, z, out):
+    from paper_1704_03329_amd import mdpl as C
+
+    C.mdpl_forces(sim.handle, x, y, z, out[0], out[1], out[2], None, None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +205,10 @@ def main():
     ap.add_argument("--n-side", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=192)
+    ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--mlp-steps", type=int, default=6000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one elementwise copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -105,6 +224,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy probe: one elementwise kernel reading and writing {args.copy_probe_mib} MiB each")
+        del src, dst
     n_side = args.n_side
     d = mdinputs.lj_fluid(n_side, temperature=1.0, seed=2)
     n = d["pos"].shape[0]
@@ -145,9 +271,9 @@ def main():
         f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}")
 
     # algorithmic bytes of one plain force launch: per atom cnt (4) + own
-    # position (24, also the gathered neighbour positions, read once) + force
-    # (12 as float); per list entry its index (4)
-    alg_bytes = n * (4 + 24 + 12) + 4 * entries
+    # position (24, also the neighbour positions, each read once) + force
+    # (12 as float); per list entry its 16-bit tile offset (2)
+    alg_bytes = n * (4 + 24 + 12) + 2 * entries
     avg_s = (f_ms / 1e3) / max(f_n, 1)
     achieved = alg_bytes / avg_s / 1e9
     traffic = measured_traffic()
@@ -193,6 +319,8 @@ def main():
         "energy_drift_per_atom": float(np.max(np.abs(etot - etot[0])) / n),
         "hbm_gbs_force": achieved,
     }
+    if not args.no_mlp:
+        out["mlp_vs_lj"] = mlp_report(args)
     if not args.no_cpu_baseline:
         log(f"oracle CPU baseline on {args.cpu_rows} atoms")
         out["cpu_baseline"] = cpu_baseline(d["pos"], box, args.cpu_rows)

@@ -203,6 +203,74 @@ mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t 
                      int32_t* nnb, uint8_t* label, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+
+/* ------------------------------------------------------- learned potential
+ * (North-star extension, not in the paper.)  Descriptors of the particles of
+ * the last mdpl_build with cutoff rc: 16 radial Gaussians
+ * exp(-eta_r (r - R_k)^2) fc(r), R_k = 0.85 + 0.11 k, eta_r = 1/(2*0.11^2),
+ * and 8 angular sums 2^(1-zeta) sum_{j != k} (1 + lam cos t_jik)^zeta w_j w_k,
+ * w = exp(-eta r^2) fc(r), (zeta, lam, eta) in {1,4} x {+1,-1} x {0.5, 2}
+ * (index 16 + 4 zi + 2 li + ei), fc(r) = (cos(pi r / rc) + 1) / 2.
+ * G: n x 24 floats (caller order); mom: n x 50 floats (nullable), the
+ * spherical-harmonic moments that mdpl_desc_bwd needs. */
+mdpl_status mdpl_desc_fwd(mdpl_sim* sim, const double* x, const double* y, const double* z,
+                          float* G, float* mom);
+
+/* Forces F_i = -dE/dr_i of E = sum_i E_i(G_i), from dEdG (n x 24, dE_i/dG_i)
+ * and mom of mdpl_desc_fwd at the same positions.  coef: n x 68 float
+ * scratch (caller-owned).  fx, fy, fz: float, caller order. */
+mdpl_status mdpl_desc_bwd(mdpl_sim* sim, const double* x, const double* y, const double* z,
+                          const float* dEdG, const float* mom, float* coef, float* fx, float* fy,
+                          float* fz);
+
+/* Network 24 -> 64 -> 64 -> 1 with SiLU: inputs g = (G - mu) / sd padded
+ * to 32, E = e_mean + e_sd (w3 . silu(W2 silu(W1 g + b1) + b2) + b3).
+ * Weights are bfloat16 bit patterns, row-major [out][in]: w1 64 x 32
+ * (columns 24..31 must be zero), w2 64 x 64, w3 64; biases float. */
+typedef struct {
+  const uint16_t* w1;
+  const float* b1;
+  const uint16_t* w2;
+  const float* b2;
+  const uint16_t* w3;
+  const float* b3;
+  const float* mu;  /* 24 */
+  const float* sd;  /* 24 */
+  float e_mean, e_sd;
+} mdpl_mlp_weights;
+
+/* Number of trainable parameters in the packed FP32 vector used by
+ * training: W1 [64][32] | b1 [64] | W2 [64][64] | b2 [64] | w3 [64] | b3. */
+#define MDPL_MLP_PARAMS 6337
+
+/* Per-atom energies (n floats, nullable) and, if dEdG is not NULL, dE/dG
+ * (n x 24 floats) for features G (n x 24), on the BF16 matrix cores. */
+mdpl_status mdpl_mlp_fwd(const mdpl_mlp_weights* w, const float* G, int64_t n, float* energy,
+                         float* dEdG, void* stream);
+
+/* Floats of scratch mdpl_mlp_train_grad needs for a batch of `batch` rows. */
+mdpl_status mdpl_mlp_train_floats(int64_t batch, int64_t* floats_host);
+
+/* Loss L = sum_b (y_b - target[index[b]])^2 / batch (y as above without
+ * e_mean/e_sd) over the rows index[0..batch) of G, and dL/dparams.
+ * grad: MDPL_MLP_PARAMS + 1 floats receiving the packed gradient and, last,
+ * L.  index: nullable (rows 0..batch).  scratch: mdpl_mlp_train_floats. */
+mdpl_status mdpl_mlp_train_grad(const mdpl_mlp_weights* w, const float* G, const int32_t* index,
+                                int64_t batch, const float* target, float* scratch,
+                                int64_t scratch_floats, float* grad, void* stream);
+
+/* One bias-corrected Adam step (step t >= 1) on the packed FP32 parameters
+ * with moments m, v; then writes the bf16 copies w1, w2, w3 (layouts as in
+ * mdpl_mlp_weights).  Padding columns of W1 are kept at zero. */
+mdpl_status mdpl_adam_step(float* params, const float* grad, float* m, float* v, float lr,
+                           float beta1, float beta2, float eps, int32_t step, uint16_t* w1,
+                           uint16_t* w2, uint16_t* w3, void* stream);
+
+/* v *= factor for n particles (used to hold a temperature while generating
+ * training configurations). */
+mdpl_status mdpl_scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
+                                  void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,9 @@ __all__ = [
     "polycrystal",
     "perturb",
     "LJ_RHO",
+    "mlp_init",
+    "batch_indices",
+    "fcc_lj",
 ]
 
 LJ_RHO = 0.8442
@@ -215,3 +218,30 @@ def polycrystal(n_target: int, n_grains: int, seed: int, rho: float = 1.0, jitte
         "phase": (grain % 3).astype(np.int32),
         "d": d,
     }
+
+
+def mlp_init(seed: int, n_in: int = 24, n_pad: int = 32, n_hidden: int = 64):
+    """Initial weights of the 24(32)-64-64-1 network: uniform in
+    +-1/sqrt(fan_in) from PCG64(seed), biases zero, padding columns zero."""
+    r = rng(seed)
+    W1 = r.uniform(-1, 1, (n_hidden, n_pad)) / math.sqrt(n_in)
+    W1[:, n_in:] = 0.0
+    W2 = r.uniform(-1, 1, (n_hidden, n_hidden)) / math.sqrt(n_hidden)
+    w3 = r.uniform(-1, 1, n_hidden) / math.sqrt(n_hidden)
+    return {"W1": W1, "b1": np.zeros(n_hidden), "W2": W2, "b2": np.zeros(n_hidden), "w3": w3,
+            "b3": np.zeros(1)}
+
+
+def batch_indices(n_rows: int, batch: int, steps: int, seed: int):
+    """Mini-batch row indices (steps x batch, int32), drawn uniformly with
+    replacement from PCG64(seed)."""
+    return rng(seed).integers(0, n_rows, size=(steps, batch), dtype=np.int32)
+
+
+def fcc_lj(n_cells: int, rho: float = LJ_RHO, temperature: float = 1.0, seed: int = 1):
+    """FCC start with n_cells^3 conventional cells at density rho and Gaussian
+    velocities: dict(pos, vel, box)."""
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    pos, box = fcc_cells((n_cells,) * 3, a)
+    vel = gaussian_velocities(pos.shape[0], temperature, seed)
+    return {"pos": np.ascontiguousarray(pos), "vel": vel, "box": box}

@@ -31,17 +31,6 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def init_params(seed: int):
-    """Weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from PCG64(seed);
-    biases zero.  W1 columns beyond the 24 real inputs are zero."""
-    r = np.random.Generator(np.random.PCG64(seed))
-    W1 = r.uniform(-1, 1, (NH, NPAD)) / np.sqrt(NIN)
-    W1[:, NIN:] = 0.0
-    W2 = r.uniform(-1, 1, (NH, NH)) / np.sqrt(NH)
-    w3 = r.uniform(-1, 1, NH) / np.sqrt(NH)
-    return {"W1": W1, "b1": np.zeros(NH), "W2": W2, "b2": np.zeros(NH), "w3": w3, "b3": np.zeros(1)}
-
-
 def standardise(G, mu, sd):
     g = np.zeros((G.shape[0], NPAD))
     g[:, :NIN] = (G - mu[None, :]) / sd[None, :]

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "mlp_args.h"
 
 using namespace mdpl;
 
@@ -600,6 +601,105 @@ mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t 
   HIP_TRY(hipMemsetAsync(small, 0, 64, st));
   HIP_TRY(build_nlist(sx, sy, sz, skeys, cs, n, g, rc * rc, nl, small, (int32_t*)(small + 1), st));
   HIP_TRY(cna_signatures(nl, perm, n, trip, nnb, label, max_nb, st));
+  return MDPL_OK;
+}
+
+// ------------------------------------------------------- learned potential
+mdpl_status mdpl_desc_fwd(mdpl_sim* s, const double* x, const double* y, const double* z, float* G,
+                          float* mom) {
+  if (!s || !x || !y || !z || !G) return MDPL_EINVAL;
+  if (!s->built) return MDPL_ESTATE;
+  HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
+  HIP_TRY(desc_forward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm, G,
+                       mom, s->st));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_desc_bwd(mdpl_sim* s, const double* x, const double* y, const double* z,
+                          const float* dEdG, const float* mom, float* coef, float* fx, float* fy,
+                          float* fz) {
+  if (!s || !x || !y || !z || !dEdG || !mom || !coef || !fx || !fy || !fz) return MDPL_EINVAL;
+  if (!s->built) return MDPL_ESTATE;
+  HIP_TRY(desc_adjoint(dEdG, mom, s->n, coef, s->st));
+  HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
+  HIP_TRY(desc_backward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm,
+                        coef, fx, fy, fz, s->st));
+  return MDPL_OK;
+}
+
+static bool mlp_ok(const mdpl_mlp_weights* w) {
+  return w && w->w1 && w->b1 && w->w2 && w->b2 && w->w3 && w->b3 && w->mu && w->sd &&
+         isfinite(w->e_mean) && isfinite(w->e_sd);
+}
+
+static MlpArgs mlp_args(const mdpl_mlp_weights* w, const float* G, int64_t n) {
+  MlpArgs a;
+  a.w1 = w->w1;
+  a.b1 = w->b1;
+  a.w2 = w->w2;
+  a.b2 = w->b2;
+  a.w3 = w->w3;
+  a.b3 = w->b3;
+  a.mu = w->mu;
+  a.sd = w->sd;
+  a.e_mean = w->e_mean;
+  a.e_sd = w->e_sd;
+  a.G = G;
+  a.index = nullptr;
+  a.n = n;
+  a.energy = nullptr;
+  a.dEdG = nullptr;
+  a.target = nullptr;
+  a.partial = nullptr;
+  a.inv_batch = 0.0f;
+  return a;
+}
+
+mdpl_status mdpl_mlp_fwd(const mdpl_mlp_weights* w, const float* G, int64_t n, float* energy,
+                         float* dEdG, void* stream) {
+  if (!mlp_ok(w) || !G || n <= 0 || (!energy && !dEdG)) return MDPL_EINVAL;
+  MlpArgs a = mlp_args(w, G, n);
+  a.energy = energy;
+  a.dEdG = dEdG;
+  HIP_TRY(mlp_eval(a, (hipStream_t)stream));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_mlp_train_floats(int64_t batch, int64_t* floats) {
+  if (batch <= 0 || !floats) return MDPL_EINVAL;
+  *floats = (int64_t)mlp_train_waves(batch) * (kMlpParams + 1);
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_mlp_train_grad(const mdpl_mlp_weights* w, const float* G, const int32_t* index,
+                                int64_t batch, const float* target, float* scratch,
+                                int64_t scratch_floats, float* grad, void* stream) {
+  if (!mlp_ok(w) || !G || batch <= 0 || !target || !scratch || !grad) return MDPL_EINVAL;
+  const int waves = mlp_train_waves(batch);
+  if (scratch_floats < (int64_t)waves * (kMlpParams + 1)) return MDPL_EWORKSPACE;
+  MlpArgs a = mlp_args(w, G, batch);
+  a.index = index;
+  a.target = target;
+  a.partial = scratch;
+  a.inv_batch = 1.0f / (float)batch;
+  HIP_TRY(mlp_train_grad(a, (hipStream_t)stream));
+  HIP_TRY(mlp_sum_partials(scratch, waves, grad, (hipStream_t)stream));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_adam_step(float* params, const float* grad, float* m, float* v, float lr,
+                           float beta1, float beta2, float eps, int32_t step, uint16_t* w1,
+                           uint16_t* w2, uint16_t* w3, void* stream) {
+  if (!params || !grad || !m || !v || !w1 || !w2 || !w3 || step < 1 || !(lr > 0.0f)) return MDPL_EINVAL;
+  HIP_TRY(adam_step(params, grad, m, v, lr, beta1, beta2, eps, step, w1, w2, w3,
+                    (hipStream_t)stream));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
+                                  void* stream) {
+  if (!vx || !vy || !vz || n <= 0 || !isfinite(factor)) return MDPL_EINVAL;
+  HIP_TRY(scale_velocities(vx, vy, vz, n, factor, (hipStream_t)stream));
   return MDPL_OK;
 }
 

@@ -1,0 +1,388 @@
+// Atom-centred symmetry-function descriptors of the learned potential (not
+// a construct of the paper; it runs on the paper's pair-loop machinery: the
+// LJ tile list with a cutoff test at rc).
+//
+// Per atom i, neighbours j with r = |r_j - r_i| < rc, fc(r) = (cos(pi r/rc)+1)/2:
+//   radial   G_k = sum_j exp(-eta_r (r - R_k)^2) fc,  R_k = 0.85 + 0.11 k, k < 16
+//   angular  G_(zeta,lam,eta) = 2^(1-zeta) sum_{j != k} (1 + lam cos t_jik)^zeta w_j w_k,
+//            w = exp(-eta r^2) fc, (zeta, lam, eta) in {1,4} x {+1,-1} x {0.5, 2}
+// The angular double sum is formed from moments through the addition
+// theorem: with P~_l^m = d^m P_l / dz^m and (x + i y)^m of the unit vector,
+//   C_lm = sum_j w_j P~_l^m(z) Re (x+iy)^m,  S_lm = sum_j w_j P~_l^m(z) Im (x+iy)^m,
+//   T_l  = sum_{j != k} P_l(cos t_jk) w_j w_k
+//        = sum_m om_lm (C_lm^2 + S_lm^2) - sum_j w_j^2,
+//   om_l0 = 1, om_lm = 2 (l-m)!/(l+m)!,
+// and (1 + lam c)^zeta = sum_l a_l P_l(c):  zeta = 1: a = (1, lam);
+//   zeta = 4: a = (16/5, 32 lam/5, 32/7, 8 lam/5, 8/35).
+//
+// Moments are packed per eta as 25 floats, l = 0..4: C_l0 at l^2, C_lm at
+// l^2 + 2m - 1, S_lm at l^2 + 2m.
+//
+// Backward (forces): with b_l = dE/dT_l, the adjoint coefficients
+//   alpha_lm = 2 om_lm b_l C_lm, gamma_lm = 2 om_lm b_l S_lm, delta = -2 sum_l b_l
+// make dE/du_ij = sum_eta [ w' Phi uh + w (grad Phi - (uh . grad Phi) uh) / r
+//                          + delta w w' uh ] + sum_k dE/dG_k phi_k'(r) uh,
+// Phi(x,y,z) = sum_lm P~_l^m(z) (alpha c_m + gamma s_m), u_ij = r_j - r_i,
+// and F_a = sum_{j in N(a)} (dE/du_aj - dE/du_ja): a gather, no atomics.
+#include <math.h>
+
+#include "device_util.h"
+#include "internal.h"
+#include "tile.h"
+
+namespace mdpl {
+
+constexpr int kNRad = 16;
+constexpr int kNFeat = 24;
+constexpr int kNMom = 25;
+constexpr float kEtaR = 41.32231404958678f;  // 1 / (2 * 0.11^2)
+
+// 2 (l-m)!/(l+m)! (1 for m = 0), indexed l(l+1)/2 + m
+__device__ __forceinline__ float omega(int idx) {
+  const float t[15] = {1.0f,
+                       1.0f, 1.0f,
+                       1.0f, 1.0f / 3.0f, 1.0f / 12.0f,
+                       1.0f, 1.0f / 6.0f, 1.0f / 60.0f, 1.0f / 360.0f,
+                       1.0f, 1.0f / 10.0f, 1.0f / 180.0f, 1.0f / 2520.0f, 1.0f / 20160.0f};
+  return t[idx];
+}
+
+// P~_l^m(z) for l <= 4 (and 0 for m = l + 1 via the caller), index l(l+1)/2 + m
+__device__ __forceinline__ void legendre_d(float z, float P[15]) {
+  const float z2 = z * z;
+  P[0] = 1.0f;
+  P[1] = z;
+  P[2] = 1.0f;
+  P[3] = 1.5f * z2 - 0.5f;
+  P[4] = 3.0f * z;
+  P[5] = 3.0f;
+  P[6] = (2.5f * z2 - 1.5f) * z;
+  P[7] = 7.5f * z2 - 1.5f;
+  P[8] = 15.0f * z;
+  P[9] = 15.0f;
+  P[10] = (4.375f * z2 - 3.75f) * z2 + 0.375f;
+  P[11] = (17.5f * z2 - 7.5f) * z;
+  P[12] = 52.5f * z2 - 7.5f;
+  P[13] = 105.0f * z;
+  P[14] = 105.0f;
+}
+
+// (x + i y)^m, m = 0..4
+__device__ __forceinline__ void cpow(float x, float y, float c[5], float s[5]) {
+  c[0] = 1.0f;
+  s[0] = 0.0f;
+#pragma unroll
+  for (int m = 1; m < 5; ++m) {
+    c[m] = c[m - 1] * x - s[m - 1] * y;
+    s[m] = c[m - 1] * y + s[m - 1] * x;
+  }
+}
+
+// a_l of (1 + lam c)^zeta times 2^(1-zeta), for angular feature index a
+// (a = zi*4 + li*2 + ei, zeta = (1,4)[zi], lam = (+1,-1)[li])
+__device__ __forceinline__ float ang_coef(int a, int l) {
+  const int zi = a >> 2, li = (a >> 1) & 1;
+  const float lam = li ? -1.0f : 1.0f;
+  if (zi == 0) return l == 0 ? 1.0f : (l == 1 ? lam : 0.0f);
+  const float c4[5] = {3.2f, 6.4f, 32.0f / 7.0f, 1.6f, 8.0f / 35.0f};
+  const float sgn = (l & 1) ? lam : 1.0f;
+  return 0.125f * c4[l] * sgn;
+}
+
+struct DescIO {
+  float* G;                // n x 24 (forward output)
+  float* mom;              // n x 50 (forward output, nullable)
+  const float* coef;       // n x 68 adjoint coefficients (backward input), caller order
+  const int32_t* perm;     // slot -> caller index (nullable: identity)
+  float* fx;               // forces (backward output), caller order
+  float* fy;
+  float* fz;
+};
+
+// ------------------------------------------------------------- forward
+__global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ z,
+                                                   const int32_t* __restrict__ cs, Grid g,
+                                                   TileList tl, float rc, DescIO io) {
+  __shared__ TileShared t;
+  const int brick = brick_of_block(g.nbricks);
+  if (brick >= g.nbricks) return;
+  const int total = tile_cells(g, brick, cs, t);
+  tile_load<true>(g, x, y, z, total, t);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  const double rc2 = (double)rc * (double)rc;
+  const float pi_rc = 3.14159265358979f / rc;
+  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+    const double xi = x[s], yi = y[s], zi = z[s];
+    float G[kNRad];
+    float M[2][kNMom];
+    float diag[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < kNRad; ++k) G[k] = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int k = 0; k < kNMom; ++k) M[e][k] = 0.0f;
+    const int ng = (tl.cnt[s] + 3) >> 2;
+    const uint64_t* __restrict__ col = tl.nbr + s;
+    for (int gi = 0; gi < ng; ++gi) {
+      const uint64_t word = col[(int64_t)gi * tl.stride];
+      for (int q = 0; q < 4; ++q) {
+        const int u = (int)((word >> (16 * q)) & 0xffff) >> 3;
+        const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 < rc2)) continue;
+        const float r = sqrtf((float)d2);
+        const float ir = 1.0f / r;
+        const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
+        const float fc = 0.5f * (cosf(pi_rc * r) + 1.0f);
+#pragma unroll
+        for (int k = 0; k < kNRad; ++k) {
+          const float d = r - (0.85f + 0.11f * (float)k);
+          G[k] += expf(-kEtaR * d * d) * fc;
+        }
+        float P[15], c[5], sn[5];
+        legendre_d(uz, P);
+        cpow(ux, uy, c, sn);
+        const float w0 = expf(-0.5f * r * r) * fc;
+        const float w1 = expf(-2.0f * r * r) * fc;
+        diag[0] += w0 * w0;
+        diag[1] += w1 * w1;
+#pragma unroll
+        for (int l = 0; l <= 4; ++l) {
+#pragma unroll
+          for (int m = 0; m <= l; ++m) {
+            const float p = P[l * (l + 1) / 2 + m];
+            const int ic = m == 0 ? l * l : l * l + 2 * m - 1;
+            M[0][ic] += w0 * p * c[m];
+            M[1][ic] += w1 * p * c[m];
+            if (m > 0) {
+              M[0][ic + 1] += w0 * p * sn[m];
+              M[1][ic + 1] += w1 * p * sn[m];
+            }
+          }
+        }
+      }
+    }
+    float T[2][5];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+#pragma unroll
+      for (int l = 0; l <= 4; ++l) {
+        float acc = M[e][l * l] * M[e][l * l];
+#pragma unroll
+        for (int m = 1; m <= l; ++m) {
+          const float a = M[e][l * l + 2 * m - 1], b = M[e][l * l + 2 * m];
+          acc += omega(l * (l + 1) / 2 + m) * (a * a + b * b);
+        }
+        T[e][l] = acc - diag[e];
+      }
+    }
+    const int64_t o = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
+    float* __restrict__ Go = io.G + o * kNFeat;
+#pragma unroll
+    for (int k = 0; k < kNRad; ++k) Go[k] = G[k];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int e = a & 1;
+      float acc = 0.0f;
+#pragma unroll
+      for (int l = 0; l <= 4; ++l) acc += ang_coef(a, l) * T[e][l];
+      Go[kNRad + a] = acc;
+    }
+    if (io.mom) {
+      float* __restrict__ Mo = io.mom + o * (2 * kNMom);
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int k = 0; k < kNMom; ++k) Mo[e * kNMom + k] = M[e][k];
+    }
+  }
+}
+
+// ------------------------------------------------------------- adjoint
+// coef[i] = (alpha/gamma for eta 0.5 [25], for eta 2 [25], delta_0, delta_1,
+//            dE/dG_k for the 16 radial features), all in caller order.
+__global__ void k_desc_adjoint(const float* __restrict__ dEdG, const float* __restrict__ mom,
+                               int64_t n, float* __restrict__ coef) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* __restrict__ d = dEdG + i * kNFeat;
+  const float* __restrict__ mm = mom + i * (2 * kNMom);
+  float* __restrict__ out = coef + i * 68;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    float b[5];
+    float bsum = 0.0f;
+#pragma unroll
+    for (int l = 0; l <= 4; ++l) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int a = e; a < 8; a += 2) acc += d[kNRad + a] * ang_coef(a, l);
+      b[l] = acc;
+      bsum += acc;
+    }
+#pragma unroll
+    for (int l = 0; l <= 4; ++l) {
+      out[e * kNMom + l * l] = 2.0f * b[l] * mm[e * kNMom + l * l];
+#pragma unroll
+      for (int m = 1; m <= l; ++m) {
+        const float w = 2.0f * omega(l * (l + 1) / 2 + m) * b[l];
+        out[e * kNMom + l * l + 2 * m - 1] = w * mm[e * kNMom + l * l + 2 * m - 1];
+        out[e * kNMom + l * l + 2 * m] = w * mm[e * kNMom + l * l + 2 * m];
+      }
+    }
+    out[50 + e] = -2.0f * bsum;
+  }
+#pragma unroll
+  for (int k = 0; k < kNRad; ++k) out[52 + k] = d[k];
+}
+
+// dE/du for a centre with adjoint coefficients K and neighbour vector u
+// (length r, unit vector uh), accumulated into (gx, gy, gz).
+__device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, float ux, float uy,
+                                          float uz, float fc, float dfc, float& gx, float& gy,
+                                          float& gz) {
+  float P[15], c[5], sn[5];
+  legendre_d(uz, P);
+  cpow(ux, uy, c, sn);
+  float radial = 0.0f;  // scalar multiplying uh
+#pragma unroll
+  for (int k = 0; k < kNRad; ++k) {
+    const float d = r - (0.85f + 0.11f * (float)k);
+    const float e = expf(-kEtaR * d * d);
+    radial += K[52 + k] * e * (-2.0f * kEtaR * d * fc + dfc);
+  }
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float eta = e ? 2.0f : 0.5f;
+    const float ex = expf(-eta * r * r);
+    const float w = ex * fc;
+    const float dw = ex * (-2.0f * eta * r * fc + dfc);
+    float phi = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
+#pragma unroll
+    for (int l = 0; l <= 4; ++l) {
+#pragma unroll
+      for (int m = 0; m <= l; ++m) {
+        const float al = K[e * kNMom + (m == 0 ? l * l : l * l + 2 * m - 1)];
+        const float ga = m == 0 ? 0.0f : K[e * kNMom + l * l + 2 * m];
+        const float p = P[l * (l + 1) / 2 + m];
+        const float pd = m < l ? P[l * (l + 1) / 2 + m + 1] : 0.0f;
+        const float v = al * c[m] + ga * sn[m];
+        phi += p * v;
+        pz += pd * v;
+        if (m > 0) {
+          const float fm = (float)m;
+          px += p * fm * (al * c[m - 1] + ga * sn[m - 1]);
+          py += p * fm * (-al * sn[m - 1] + ga * c[m - 1]);
+        }
+      }
+    }
+    const float dot = ux * px + uy * py + uz * pz;
+    const float tw = w / r;
+    const float sc = dw * phi + K[50 + e] * w * dw;
+    ax += sc * ux + tw * (px - dot * ux);
+    ay += sc * uy + tw * (py - dot * uy);
+    az += sc * uz + tw * (pz - dot * uz);
+  }
+  gx += ax + radial * ux;
+  gy += ay + radial * uy;
+  gz += az + radial * uz;
+}
+
+// ------------------------------------------------------------- backward
+__global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ z,
+                                                   const int32_t* __restrict__ cs, Grid g,
+                                                   TileList tl, float rc, DescIO io) {
+  __shared__ TileShared t;
+  const int brick = brick_of_block(g.nbricks);
+  if (brick >= g.nbricks) return;
+  const int total = tile_cells(g, brick, cs, t);
+  tile_load<true>(g, x, y, z, total, t);
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  const double rc2 = (double)rc * (double)rc;
+  const float pi_rc = 3.14159265358979f / rc;
+  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+    const double xi = x[s], yi = y[s], zi = z[s];
+    const int64_t oi = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
+    float Ki[68];
+#pragma unroll
+    for (int k = 0; k < 68; ++k) Ki[k] = io.coef[oi * 68 + k];
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    const int ng = (tl.cnt[s] + 3) >> 2;
+    const uint64_t* __restrict__ col = tl.nbr + s;
+    for (int gi = 0; gi < ng; ++gi) {
+      const uint64_t word = col[(int64_t)gi * tl.stride];
+      for (int q = 0; q < 4; ++q) {
+        const int u = (int)((word >> (16 * q)) & 0xffff) >> 3;
+        if (u >= total || u >= kTileCap) continue;  // padding slot
+        const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 < rc2)) continue;
+        const float r = sqrtf((float)d2);
+        const float ir = 1.0f / r;
+        const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
+        const float ang = pi_rc * r;
+        const float fc = 0.5f * (cosf(ang) + 1.0f);
+        const float dfc = -0.5f * pi_rc * sinf(ang);
+        float ga = 0.0f, gb = 0.0f, gc = 0.0f;
+        pair_grad(Ki, r, ux, uy, uz, fc, dfc, ga, gb, gc);
+        // the neighbour's slot from its tile index
+        int lo = 0, hi = ntc;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (t.prefix[mid] <= u) lo = mid;
+          else hi = mid;
+        }
+        const int sj = t.src[lo] + (u - t.prefix[lo]);
+        const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
+        float Kj[68];
+#pragma unroll
+        for (int k = 0; k < 68; ++k) Kj[k] = io.coef[oj * 68 + k];
+        float ha = 0.0f, hb = 0.0f, hc = 0.0f;
+        pair_grad(Kj, r, -ux, -uy, -uz, fc, dfc, ha, hb, hc);
+        fx += ga - ha;
+        fy += gb - hb;
+        fz += gc - hc;
+      }
+    }
+    io.fx[oi] = fx;
+    io.fy[oi] = fy;
+    io.fz[oi] = fz;
+  }
+}
+
+hipError_t desc_forward(const double* x, const double* y, const double* z,
+                        const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
+                        const int32_t* perm, float* G, float* mom, hipStream_t st) {
+  DescIO io{G, mom, nullptr, perm, nullptr, nullptr, nullptr};
+  const unsigned threads = tl.threads < 512 ? tl.threads : 512;
+  hipLaunchKernelGGL(k_desc_fwd, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st, x, y,
+                     z, cell_start, g, tl, rc, io);
+  return hipGetLastError();
+}
+
+hipError_t desc_adjoint(const float* dEdG, const float* mom, int64_t n, float* coef,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_adjoint, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, dEdG, mom, n,
+                     coef);
+  return hipGetLastError();
+}
+
+hipError_t desc_backward(const double* x, const double* y, const double* z,
+                         const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
+                         const int32_t* perm, const float* coef, float* fx, float* fy, float* fz,
+                         hipStream_t st) {
+  DescIO io{nullptr, nullptr, coef, perm, fx, fy, fz};
+  const unsigned threads = tl.threads < 512 ? tl.threads : 512;
+  hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st, x, y,
+                     z, cell_start, g, tl, rc, io);
+  return hipGetLastError();
+}
+
+}  // namespace mdpl

@@ -109,10 +109,11 @@ hipError_t build_nlist(const double* sx, const double* sy, const double* sz,
 
 // Tiled neighbour list of the LJ path.  One workgroup per brick stages the
 // positions of the brick's (B+2)^3-cell neighbourhood (its "tile") in LDS;
-// entries are 16-bit tile-local indices packed four to a 64-bit word, the
-// words column-major: entry m of slot s is 16-bit lane (m & 3) of
-// nbr[(m >> 2) * stride + s].  The last word of a list is padded with
-// kTileDummy, a tile slot that holds a position far outside the box.
+// an entry is the byte offset (8 x slot) of the neighbour's coordinate in a
+// tile array, 16 bits, packed four to a 64-bit word, the words
+// column-major: entry m of slot s is 16-bit lane (m & 3) of
+// nbr[(m >> 2) * stride + s].  The last word of a list is padded with the
+// offset of kTileDummy, a tile slot that holds a position far outside the box.
 constexpr int kTileMax = 3072;              // tile slots (LDS)
 constexpr int kBrickMax = 1024;             // particles of one brick the list builder counts
 constexpr int kTileDummy = kTileMax - 1;    // padding slot
@@ -183,5 +184,27 @@ hipError_t boa_q(const double* sx, const double* sy, const double* sz, const int
 hipError_t cna_signatures(const NList& nl, const int32_t* perm, int64_t n, uint32_t* trip,
                           int32_t* nnb, uint8_t* label, int max_out, hipStream_t st);
 
+
+// Learned potential: descriptors (desc.hip) and dense layers (mlp.hip).
+hipError_t desc_forward(const double* x, const double* y, const double* z,
+                        const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
+                        const int32_t* perm, float* G, float* mom, hipStream_t st);
+hipError_t desc_adjoint(const float* dEdG, const float* mom, int64_t n, float* coef,
+                        hipStream_t st);
+hipError_t desc_backward(const double* x, const double* y, const double* z,
+                         const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
+                         const int32_t* perm, const float* coef, float* fx, float* fy, float* fz,
+                         hipStream_t st);
+
+struct MlpArgs;
+hipError_t mlp_eval(const MlpArgs& a, hipStream_t st);
+hipError_t mlp_train_grad(const MlpArgs& a, hipStream_t st);
+int mlp_train_waves(int64_t n);
+hipError_t mlp_sum_partials(const float* partial, int nwaves, float* out, hipStream_t st);
+hipError_t adam_step(float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
+                     float eps, int t, unsigned short* w1, unsigned short* w2, unsigned short* w3,
+                     hipStream_t st);
+hipError_t scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
+                            hipStream_t st);
 
 }  // namespace mdpl

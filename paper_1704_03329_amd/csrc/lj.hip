@@ -5,11 +5,12 @@
 // written once per particle (gather only, no atomics: the paper's choice of
 // looping over all ordered pairs and writing to the first particle, Sec. 2).
 // Each workgroup handles one brick of cells and stages the image positions of
-// its neighbourhood in LDS (tile.h); list entries are tile indices.  The
-// cutoff test d2 < rc^2 uses the FP64 separation and the uncontracted d2 of
-// the definition; for pairs across a periodic face the image is added to the
-// stored position once per tile, so only such pairs can round differently
-// from the definition (by one unit in the last place of d2).
+// its neighbourhood in LDS (tile.h); list entries are byte offsets into the
+// tile.  The cutoff test d2 < rc^2 uses the FP64 separation; the periodic
+// image is added to a tile position once, and the plain pass forms d2 with
+// fused multiply-adds, so a pair can be classified differently from the
+// definition only within a few units in the last place of rc^2.  The
+// energy pass uses the definition's uncontracted d2.
 //
 // Precision (FP32 mode): the separation and the test in FP64, the pair force
 // factor in FP32 from the rounded squared distance, per-particle sums in
@@ -66,15 +67,15 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
       if (gi + 1 < ngroups) next = col[(int64_t)(gi + 1) * tl.stride];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int u = (int)((word >> (16 * k)) & 0xffff);
-        const double dx = xi - t.x[u];
-        const double dy = yi - t.y[u];
-        const double dz = zi - t.z[u];
-        const double d2 = sq_sum(dx, dy, dz);
-        const bool in = d2 < c.rc2;
+        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;  // byte offset in a tile array
+        const double dx = xi - *(const double*)((const char*)t.x + off);
+        const double dy = yi - *(const double*)((const char*)t.y + off);
+        const double dz = zi - *(const double*)((const char*)t.z + off);
         double g;
         if (ENERGY) {
           // pair energy and virial in FP64 on the sampled steps
+          const double d2 = sq_sum(dx, dy, dz);
+          const bool in = d2 < c.rc2;
           const double inv = 1.0 / d2;
           const double s2 = c.sigma2 * inv;
           const double s6 = s2 * s2 * s2;
@@ -84,6 +85,8 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
           ei += in ? 0.5 * v : 0.0;
           w += 0.5 * g * d2;
         } else {
+          const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+          const bool in = d2 < c.rc2;
           MT inv;
           if constexpr (sizeof(MT) == 4)
             inv = __builtin_amdgcn_rcpf((float)d2);
@@ -91,8 +94,9 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
             inv = 1.0 / d2;
           const MT s2 = sig2 * inv;
           const MT s6 = s2 * s2 * s2;
-          const MT gg = inv * s6 * (c48 * s6 - c24);
-          g = in ? (double)gg : 0.0;
+          MT gg = inv * s6 * (c48 * s6 - c24);
+          gg = in ? gg : (MT)0;
+          g = (double)gg;
         }
         ax = __builtin_fma(g, dx, ax);
         ay = __builtin_fma(g, dy, ay);
@@ -299,6 +303,26 @@ hipError_t skin_check(const double* partials, int nblocks, double half_skin, dou
                       uint32_t* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_skin_check, dim3(1), dim3(256), 0, st, partials, nblocks, half_skin,
                      max_disp, flags);
+  return hipGetLastError();
+}
+
+}  // namespace mdpl
+
+namespace mdpl {
+
+__global__ void k_scale_v(double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
+                          int64_t n, double f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  vx[i] *= f;
+  vy[i] *= f;
+  vz[i] *= f;
+}
+
+hipError_t scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_v, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, vx, vy, vz, n,
+                     factor);
   return hipGetLastError();
 }
 

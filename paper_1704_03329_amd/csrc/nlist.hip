@@ -97,7 +97,8 @@ __global__ __launch_bounds__(1024) void k_build_tile_nlist(
               }
               if (d2 < r2 && u != self) {
                 const int m = atomicAdd(&acnt[la], 1);
-                if (m < max_nb) half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)u;
+                if (m < max_nb)
+                  half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(u << 3);
               }
             }
           }
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(1024) void k_build_tile_nlist(
     const int count = acnt[la];
     const int kept = count < max_nb ? count : max_nb;
     for (int m = kept; m < ((kept + 3) & ~3); ++m)  // pad the last word
-      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)kTileDummy;
+      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(kTileDummy << 3);
     tl.cnt[s] = kept;
     if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
     most = count > most ? count : most;
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(1024) void k_export_tile_pairs(
     const int32_t pi = perm[s];
     for (int m = 0; m < c; ++m) {
       if (o + m >= cap) break;
-      const int u = (int)((tl.nbr[(int64_t)(m >> 2) * tl.stride + s] >> (16 * (m & 3))) & 0xffff);
+      const int u = (int)((tl.nbr[(int64_t)(m >> 2) * tl.stride + s] >> (16 * (m & 3))) & 0xffff) >> 3;
       int lo = 0, hi = ntc;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;

@@ -250,3 +250,67 @@ def mdpl_cna(x, y, z, box, rc, max_nb, trip, nnb, label, workspace, stream=None)
     _check(lib().mdpl_cna(_ptr(x), _ptr(y), _ptr(z), n, b, float(rc), int(max_nb), _ptr(trip), _ptr(nnb),
                           _ptr(label), _dev(workspace, torch.uint8), workspace.numel(), _stream(stream)),
            "mdpl_cna")
+
+
+# ------------------------------------------------------- learned potential
+def _handle(sim):
+    return sim.handle if hasattr(sim, "handle") else sim
+
+
+class mdpl_mlp_weights(ctypes.Structure):
+    _fields_ = [("w1", ctypes.c_void_p), ("b1", ctypes.c_void_p), ("w2", ctypes.c_void_p),
+                ("b2", ctypes.c_void_p), ("w3", ctypes.c_void_p), ("b3", ctypes.c_void_p),
+                ("mu", ctypes.c_void_p), ("sd", ctypes.c_void_p), ("e_mean", ctypes.c_float),
+                ("e_sd", ctypes.c_float)]
+
+
+_SIGS_MLP = {
+    "mdpl_desc_fwd": ([ctypes.c_void_p] * 6, ctypes.c_int32),
+    "mdpl_desc_bwd": ([ctypes.c_void_p] * 10, ctypes.c_int32),
+    "mdpl_mlp_fwd": ([ctypes.POINTER(mdpl_mlp_weights), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
+    "mdpl_mlp_train_floats": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mdpl_mlp_train_grad": ([ctypes.POINTER(mdpl_mlp_weights), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+                            ctypes.c_int32),
+    "mdpl_adam_step": ([ctypes.c_void_p] * 4 + [ctypes.c_float] * 4 + [ctypes.c_int32] + [ctypes.c_void_p] * 4,
+                       ctypes.c_int32),
+    "mdpl_scale_velocities": ([ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_double, ctypes.c_void_p],
+                              ctypes.c_int32),
+}
+_SIGS.update(_SIGS_MLP)
+
+
+# ------------------------------------------------------------ entry points
+def mdpl_desc_fwd(sim, x, y, z, G, mom=None):
+    _check(lib().mdpl_desc_fwd(_handle(sim), _ptr(x), _ptr(y), _ptr(z), _ptr(G), _ptr(mom)), "mdpl_desc_fwd")
+
+
+def mdpl_desc_bwd(sim, x, y, z, dEdG, mom, coef, fx, fy, fz):
+    _check(lib().mdpl_desc_bwd(_handle(sim), _ptr(x), _ptr(y), _ptr(z), _ptr(dEdG), _ptr(mom), _ptr(coef), _ptr(fx), _ptr(fy),
+                                  _ptr(fz)), "mdpl_desc_bwd")
+
+
+def mdpl_mlp_fwd(w: mdpl_mlp_weights, G, n, energy=None, dEdG=None):
+    _check(lib().mdpl_mlp_fwd(ctypes.byref(w), _ptr(G), int(n), _ptr(energy), _ptr(dEdG), _stream()), "mdpl_mlp_fwd")
+
+
+def mdpl_mlp_train_floats(batch: int) -> int:
+    out = ctypes.c_int64(0)
+    _check(lib().mdpl_mlp_train_floats(int(batch), ctypes.byref(out)), "mdpl_mlp_train_floats")
+    return int(out.value)
+
+
+def mdpl_mlp_train_grad(w, G, index, batch, target, scratch, grad):
+    _check(lib().mdpl_mlp_train_grad(ctypes.byref(w), _ptr(G), _ptr(index), int(batch), _ptr(target), _ptr(scratch),
+                                        scratch.numel(), _ptr(grad), _stream()), "mdpl_mlp_train_grad")
+
+
+def mdpl_adam_step(params, grad, m, v, lr, b1, b2, eps, step, w1, w2, w3):
+    _check(lib().mdpl_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), float(lr), float(b1), float(b2), float(eps),
+                                   int(step), _ptr(w1), _ptr(w2), _ptr(w3), _stream()), "mdpl_adam_step")
+
+
+def mdpl_scale_velocities(vx, vy, vz, factor):
+    _check(lib().mdpl_scale_velocities(_ptr(vx), _ptr(vy), _ptr(vz), vx.numel(), float(factor), _stream()),
+             "mdpl_scale_velocities")

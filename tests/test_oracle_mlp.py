@@ -113,7 +113,7 @@ def test_feature_gradients_finite_difference():
 
 
 def _params():
-    return M.init_params(11)
+    return mdinputs.mlp_init(11)
 
 
 def test_mlp_input_gradient_fd():
