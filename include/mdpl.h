@@ -271,6 +271,30 @@ mdpl_status mdpl_adam_step(float* params, const float* grad, float* m, float* v,
 mdpl_status mdpl_scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
                                   void* stream);
 
+/* Floats of caller workspace mdpl_run_mlp needs for n particles (167 n:
+ * features, moments, energies, dE/dG, adjoint coefficients). */
+mdpl_status mdpl_mlp_run_floats(int64_t n, int64_t* floats_host);
+
+/* mdpl_run with the learned potential as the force field (Alg.
+ * VelocityVerlet with list reuse, Sec. 3.1; forces F = -grad sum_i E_i).
+ * Same state arrays, in-place reordering, ids, flags and rebuild rule as
+ * mdpl_run; the sim must have precision MDPL_FP32 (forces are float) and
+ * its rc is the descriptor cutoff.  thermo rows: KE, sum_i E_i (FP64 sum
+ * of the FP32 per-atom energies), 0 (no virial), max displacement.  ws:
+ * mdpl_mlp_run_floats floats (MDPL_EWORKSPACE if fewer); its contents are
+ * scratch.  Force-pass timing (mdpl_set_timing) is recorded as for LJ. */
+mdpl_status mdpl_run_mlp(mdpl_sim* sim, const mdpl_mlp_weights* w, float* ws, int64_t ws_floats,
+                         double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                         float* fx, float* fy, float* fz, int32_t* ids, int64_t nsteps,
+                         int32_t sample_every, double* thermo);
+
+/* out[0] = sum_i |f_i - g_i|^2, out[1] = sum_i |g_i|^2 over the sim's n
+ * particles (FP64, fixed order): the force error of one force field (f,
+ * float) against another (g, FP64) at the same positions.  out: 2 doubles
+ * on the device; uses the sim's partials and stream. */
+mdpl_status mdpl_force_error(mdpl_sim* sim, const float* fx, const float* fy, const float* fz,
+                             const double* gx, const double* gy, const double* gz, double* out);
+
 #ifdef __cplusplus
 }
 #endif

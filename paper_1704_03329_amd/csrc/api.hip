@@ -408,11 +408,16 @@ mdpl_status mdpl_kernel_time(mdpl_sim* s, int32_t which, double* ms, int64_t* la
   return MDPL_OK;
 }
 
-mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, double* vy,
-                     double* vz, void* fx, void* fy, void* fz, int32_t* ids, int64_t nsteps,
-                     int32_t sample_every, double* thermo) {
-  if (!s || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids) return MDPL_EINVAL;
-  if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The time loop of Alg. VelocityVerlet with list reuse (Sec. 3.1), shared by
+// the LJ and learned-potential runs.  force(cur, energy, pe_w_dst, slot)
+// fills cur.f* from cur positions (and PE, W into pe_w_dst on sampled steps).
+template <typename ForceFn>
+mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t sample_every,
+                     double* thermo, ForceFn force) {
   const int64_t n = s->n;
   const int prec = s->p.precision;
   const int ns = s->p.reuse_every;
@@ -420,7 +425,6 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
   const double h = dt / (2.0 * s->p.mass);
   const double half_skin = 0.5 * s->p.skin;
   const double ke_scale = 0.5 * s->p.mass;
-  StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
   StateArrays alt{s->sx, s->sy, s->sz, s->avx, s->avy, s->avz, s->afx, s->afy, s->afz, s->aids};
   StateArrays cur = user, other = alt;
   bool have_ref = false;
@@ -450,8 +454,7 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
 
   mdpl_status r = rebuild();
   if (r != MDPL_OK) return r;
-  r = launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr, sampled(0), nullptr,
-                   sampled(0) ? row(0) + 1 : nullptr, prec, -1);
+  r = force(cur, sampled(0), sampled(0) ? row(0) + 1 : nullptr, -1);
   if (r != MDPL_OK) return r;
   if (sampled(0)) {
     int nb = 0;
@@ -471,8 +474,7 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
       if (r != MDPL_OK) return r;
     }
     const bool en = sampled(step);
-    r = launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr, en, nullptr,
-                     en ? row(step) + 1 : nullptr, prec, en ? 1 : 0);
+    r = force(cur, en, en ? row(step) + 1 : nullptr, en ? 1 : 0);
     if (r != MDPL_OK) return r;
     if (en) HIP_TRY(hipMemcpyAsync(row(step) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
   }
@@ -503,6 +505,24 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
     HIP_TRY(hipMemcpyAsync(user.ids, cur.ids, 4 * (size_t)n, hipMemcpyDeviceToDevice, s->st));
   }
   return MDPL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, double* vy,
+                     double* vz, void* fx, void* fy, void* fz, int32_t* ids, int64_t nsteps,
+                     int32_t sample_every, double* thermo) {
+  if (!s || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids) return MDPL_EINVAL;
+  if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
+  const int prec = s->p.precision;
+  StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
+  return run_loop(s, user, nsteps, sample_every, thermo,
+                  [&](const StateArrays& cur, bool en, double* pe_w, int slot) {
+                    return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr,
+                                        en, nullptr, pe_w, prec, slot);
+                  });
 }
 
 // ------------------------------------------------------------ analysis
@@ -693,6 +713,71 @@ mdpl_status mdpl_adam_step(float* params, const float* grad, float* m, float* v,
   if (!params || !grad || !m || !v || !w1 || !w2 || !w3 || step < 1 || !(lr > 0.0f)) return MDPL_EINVAL;
   HIP_TRY(adam_step(params, grad, m, v, lr, beta1, beta2, eps, step, w1, w2, w3,
                     (hipStream_t)stream));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_mlp_run_floats(int64_t n, int64_t* floats) {
+  if (n <= 0 || !floats) return MDPL_EINVAL;
+  *floats = (int64_t)kMlpRunFloats * n;
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int64_t ws_floats,
+                         double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                         float* fx, float* fy, float* fz, int32_t* ids, int64_t nsteps,
+                         int32_t sample_every, double* thermo) {
+  if (!s || !mlp_ok(w) || !ws || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids)
+    return MDPL_EINVAL;
+  if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
+  if (s->p.precision != MDPL_FP32) return MDPL_EINVAL;
+  const int64_t n = s->n;
+  if (ws_floats < (int64_t)kMlpRunFloats * n) return MDPL_EWORKSPACE;
+  float* G = ws;
+  float* mom = G + 24 * n;
+  float* e = mom + 50 * n;
+  float* dG = e + n;
+  float* coef = dG + 24 * n;
+  const float rc = (float)s->p.rc;
+  StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
+  return run_loop(s, user, nsteps, sample_every, thermo,
+                  [&](const StateArrays& cur, bool en, double* pe_w, int slot) -> mdpl_status {
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (s->timing && slot >= 0) {
+                      HIP_TRY(hipEventCreate(&e0));
+                      HIP_TRY(hipEventCreate(&e1));
+                      HIP_TRY(hipEventRecord(e0, s->st));
+                    }
+                    HIP_TRY(desc_forward(cur.x, cur.y, cur.z, s->cell_start, s->g, s->tl, rc,
+                                         nullptr, G, mom, s->st));
+                    MlpArgs a = mlp_args(w, G, n);
+                    a.energy = e;
+                    a.dEdG = dG;
+                    HIP_TRY(mlp_eval(a, s->st));
+                    HIP_TRY(desc_adjoint(dG, mom, n, coef, s->st));
+                    HIP_TRY(desc_backward(cur.x, cur.y, cur.z, s->cell_start, s->g, s->tl, rc,
+                                          nullptr, coef, (float*)cur.fx, (float*)cur.fy,
+                                          (float*)cur.fz, s->st));
+                    if (e1) {
+                      HIP_TRY(hipEventRecord(e1, s->st));
+                      s->tm.ev[slot].push_back(e0);
+                      s->tm.ev[slot].push_back(e1);
+                    }
+                    if (en && pe_w) {
+                      int nb = 0;
+                      HIP_TRY(sum_f32(e, n, s->partials, s->st, &nb));
+                      HIP_TRY(reduce_partials(s->partials, nb, 1, 1, pe_w, 1.0, s->st));
+                      HIP_TRY(hipMemsetAsync(pe_w + 1, 0, 8, s->st));
+                    }
+                    return MDPL_OK;
+                  });
+}
+
+mdpl_status mdpl_force_error(mdpl_sim* s, const float* fx, const float* fy, const float* fz,
+                             const double* gx, const double* gy, const double* gz, double* out) {
+  if (!s || !fx || !fy || !fz || !gx || !gy || !gz || !out) return MDPL_EINVAL;
+  int nb = 0;
+  HIP_TRY(force_diff(fx, fy, fz, gx, gy, gz, s->n, s->partials, s->st, &nb));
+  HIP_TRY(reduce_partials(s->partials, nb, 2, 2, out, 1.0, s->st));
   return MDPL_OK;
 }
 

@@ -24,6 +24,9 @@
 //                          + delta w w' uh ] + sum_k dE/dG_k phi_k'(r) uh,
 // Phi(x,y,z) = sum_lm P~_l^m(z) (alpha c_m + gamma s_m), u_ij = r_j - r_i,
 // and F_a = sum_{j in N(a)} (dE/du_aj - dE/du_ja): a gather, no atomics.
+// Under u -> -u the basis P~_l^m(z) (x+iy)^m changes sign for odd l and the
+// radial and diagonal terms are even, so dE/du_aj - dE/du_ja is one
+// evaluation of dE/du_aj with K_a + K_j', K_j' = K_j with odd-l moments negated.
 #include <math.h>
 
 #include "device_util.h"
@@ -299,11 +302,12 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
                                                    const int32_t* __restrict__ cs, Grid g,
                                                    TileList tl, float rc, DescIO io) {
   __shared__ TileShared t;
+  __shared__ int slot_of[kTileMax];
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
   tile_load<true>(g, x, y, z, total, t);
-  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  tile_slots(g, total, t, slot_of);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const double rc2 = (double)rc * (double)rc;
   const float pi_rc = 3.14159265358979f / rc;
@@ -330,25 +334,19 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
         const float ang = pi_rc * r;
         const float fc = 0.5f * (cosf(ang) + 1.0f);
         const float dfc = -0.5f * pi_rc * sinf(ang);
-        float ga = 0.0f, gb = 0.0f, gc = 0.0f;
-        pair_grad(Ki, r, ux, uy, uz, fc, dfc, ga, gb, gc);
-        // the neighbour's slot from its tile index
-        int lo = 0, hi = ntc;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (t.prefix[mid] <= u) lo = mid;
-          else hi = mid;
-        }
-        const int sj = t.src[lo] + (u - t.prefix[lo]);
+        const int sj = slot_of[u];
         const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
-        float Kj[68];
+        // Both terms of the pair in one evaluation: the basis has parity
+        // (-1)^l, so -dE_j/du_ji equals dE/du_ij of a centre whose odd-l
+        // coefficients are those of j with the sign flipped (linear in K).
+        float K[68];
 #pragma unroll
-        for (int k = 0; k < 68; ++k) Kj[k] = io.coef[oj * 68 + k];
-        float ha = 0.0f, hb = 0.0f, hc = 0.0f;
-        pair_grad(Kj, r, -ux, -uy, -uz, fc, dfc, ha, hb, hc);
-        fx += ga - ha;
-        fy += gb - hb;
-        fz += gc - hc;
+        for (int k = 0; k < 68; ++k) {
+          const int l = k < 50 ? (k % kNMom < 1 ? 0 : (k % kNMom < 4 ? 1 : (k % kNMom < 9 ? 2 : (k % kNMom < 16 ? 3 : 4)))) : 0;
+          const float kj = io.coef[oj * 68 + k];
+          K[k] = Ki[k] + ((l & 1) ? -kj : kj);
+        }
+        pair_grad(K, r, ux, uy, uz, fc, dfc, fx, fy, fz);
       }
     }
     io.fx[oi] = fx;

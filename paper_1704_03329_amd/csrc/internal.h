@@ -206,5 +206,10 @@ hipError_t adam_step(float* p, const float* g, float* m, float* v, float lr, flo
                      hipStream_t st);
 hipError_t scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
                             hipStream_t st);
+// FP64 block partials of a float array, and of (|f - g|^2, |g|^2) per particle.
+hipError_t sum_f32(const float* v, int64_t n, double* partials, hipStream_t st, int* nblocks_out);
+hipError_t force_diff(const float* fx, const float* fy, const float* fz, const double* gx,
+                      const double* gy, const double* gz, int64_t n, double* partials,
+                      hipStream_t st, int* nblocks_out);
 
 }  // namespace mdpl

@@ -14,6 +14,7 @@
 // Partials are written per wave and reduced in a fixed order.
 #include <math.h>
 
+#include "device_util.h"
 #include "internal.h"
 #include "mlp_args.h"
 
@@ -435,6 +436,58 @@ hipError_t adam_step(float* p, const float* g, float* m, float* v, float lr, flo
   const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
   hipLaunchKernelGGL(k_adam, dim3((kNParam + 255) / 256), dim3(256), 0, st, p, g, m, v, lr, b1, b2,
                      eps, c1, c2, w1, w2, w3);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ reductions
+// partials[b] = sum of v over block b (FP64, fixed order).
+__global__ __launch_bounds__(256) void k_sum_f32(const float* __restrict__ v, int64_t n,
+                                                 double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double t = block_sum256(i < n ? (double)v[i] : 0.0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+hipError_t sum_f32(const float* v, int64_t n, double* partials, hipStream_t st, int* nblocks_out) {
+  const unsigned nb = (unsigned)div_up(n, 256);
+  *nblocks_out = (int)nb;
+  hipLaunchKernelGGL(k_sum_f32, dim3(nb), dim3(256), 0, st, v, n, partials);
+  return hipGetLastError();
+}
+
+// partials[2b] = sum |f - g|^2, partials[2b+1] = sum |g|^2 over block b.
+__global__ __launch_bounds__(256) void k_force_diff(const float* __restrict__ fx,
+                                                    const float* __restrict__ fy,
+                                                    const float* __restrict__ fz,
+                                                    const double* __restrict__ gx,
+                                                    const double* __restrict__ gy,
+                                                    const double* __restrict__ gz, int64_t n,
+                                                    double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0, r = 0.0;
+  if (i < n) {
+    const double a = (double)fx[i] - gx[i], b = (double)fy[i] - gy[i], c = (double)fz[i] - gz[i];
+    d = a * a + b * b + c * c;
+    r = gx[i] * gx[i] + gy[i] * gy[i] + gz[i] * gz[i];
+  }
+  const double td = block_sum256(d, sh);
+  __syncthreads();
+  const double tr = block_sum256(r, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = td;
+    partials[2 * blockIdx.x + 1] = tr;
+  }
+}
+
+hipError_t force_diff(const float* fx, const float* fy, const float* fz, const double* gx,
+                      const double* gy, const double* gz, int64_t n, double* partials,
+                      hipStream_t st, int* nblocks_out) {
+  const unsigned nb = (unsigned)div_up(n, 256);
+  *nblocks_out = (int)nb;
+  hipLaunchKernelGGL(k_force_diff, dim3(nb), dim3(256), 0, st, fx, fy, fz, gx, gy, gz, n,
+                     partials);
   return hipGetLastError();
 }
 

@@ -25,21 +25,29 @@ namespace mdpl {
 // ------------------------------------------------------------------ LJ list
 // One wave per home cell at a time.  The cell's particles (na <= 64 per
 // pass) are spread over the 64 lanes as na x K (K = 64 / na): lane
-// (a, k) tests particle a against candidates k, k+K, k+2K, ... of every
-// stencil cell, so all lanes walk the same 27 cells together and lanes with
-// equal k read the same tile slot.  Accepted neighbours get their rank from
-// a per-particle LDS counter and are stored as 16-bit halves of the list
-// words; a final pass pads the last word and writes the counts.
+// (a, k) = a + na k tests particle a against candidates k, k+K, k+2K, ...
+// of every stencil cell, so all lanes walk the same 27 cells together and
+// lanes with equal k read the same tile slot.
+//
+// Ranks come from wave ballots, not atomics: in each step the accepted
+// lanes of particle a are counted below the lane (mbcnt) and in total
+// (popcount), so a list is ordered by candidate and is the same on every
+// run.  Lists are staged in LDS for a batch of the brick's particles and
+// written out as whole 64-bit words, consecutive slots in consecutive
+// words (coalesced), the last word padded with the dummy entry.
 //
 // Cells without a periodic image (code 0) use the stored positions directly,
 // which is exactly the definition's arithmetic; image cells fall back to the
 // exact conditional minimum image.
+constexpr int kStageEntries = 36864;  // 16-bit entries staged per workgroup (72 KB)
+
 __global__ __launch_bounds__(1024) void k_build_tile_nlist(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
     TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
   __shared__ TileShared t;
-  __shared__ int acnt[kBrickMax];
+  __shared__ uint16_t stage[kStageEntries];
+  __shared__ int scount[kBrickMax];
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
@@ -47,77 +55,113 @@ __global__ __launch_bounds__(1024) void k_build_tile_nlist(
   const int nbrick = s1 - s0;
   if (threadIdx.x == 0 && (total > kTileCap || nbrick > kBrickMax))
     atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
-  for (int a = threadIdx.x; a < kBrickMax; a += blockDim.x) acnt[a] = 0;
   tile_load<false>(g, x, y, z, total, t);  // ends with a barrier
   const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
   const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
   const int TX = g.B[0] + 2, TXY = TX * (g.B[1] + 2);
   const int max_nb = tl.max_nb;
-  uint16_t* __restrict__ half = (uint16_t*)tl.nbr;
+  const int mw = (max_nb + 3) >> 2;  // words per particle
+  int per = kStageEntries / (4 * mw);
+  per = per < kBrickMax ? per : kBrickMax;
+  const int nb = nbrick < kBrickMax ? nbrick : kBrickMax;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   int bx, by, bz;
   brick_coords(g, brick, bx, by, bz);
-  for (int lc = wave; lc < g.V; lc += nwaves) {
-    const int lx = lc % g.B[0], ly = (lc / g.B[0]) % g.B[1], lz = lc / (g.B[0] * g.B[1]);
-    // the last brick along an axis may be partial: its missing cells would
-    // alias periodic images of another brick's cells
-    if (bx * g.B[0] + lx >= g.nc[0] || by * g.B[1] + ly >= g.nc[1] || bz * g.B[2] + lz >= g.nc[2])
-      continue;
-    const int tc0 = ((lz + 1) * (g.B[1] + 2) + (ly + 1)) * TX + (lx + 1);
-    const int ncell = t.prefix[tc0 + 1] - t.prefix[tc0];
-    const int slot0 = t.src[tc0];
-    for (int a0 = 0; a0 < ncell; a0 += 64) {
-      const int na = ncell - a0 < 64 ? ncell - a0 : 64;
-      const int K = 64 / na;
-      const int a = a0 + lane % na, k = lane / na;
-      const bool active = k < K;
-      const int self = t.prefix[tc0] + a;
-      const int s = slot0 + a;          // sorted slot of particle a
-      const int la = s - s0;            // its index within the brick
-      const bool ok = active && self < kTileCap && la >= 0 && la < kBrickMax && s < s1;
-      const double xi = ok ? t.x[self] : 0.0, yi = ok ? t.y[self] : 0.0, zi = ok ? t.z[self] : 0.0;
-      for (int oz = -1; oz <= 1; ++oz) {
-        for (int oy = -1; oy <= 1; ++oy) {
-          const int tcl = tc0 + oz * TXY + oy * TX - 1;
-          for (int tc = tcl; tc < tcl + 3; ++tc) {
-            const int code = t.code[tc];
-            int ue = t.prefix[tc + 1];
-            ue = ue < kTileCap ? ue : kTileCap;
-            const int ub = t.prefix[tc] + k;
-            if (!ok) continue;
-            for (int u = ub; u < ue; u += K) {
-              double d2;
-              if (code == 21) {  // no image: (1,1,1) in the 2-bit fields
+  int most = 0;
+  for (int b0 = 0; b0 < nb; b0 += per) {
+    const int b1 = b0 + per < nb ? b0 + per : nb;
+    const int np = b1 - b0;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) scount[p] = 0;
+    __syncthreads();
+    for (int lc = wave; lc < g.V; lc += nwaves) {
+      const int lx = lc % g.B[0], ly = (lc / g.B[0]) % g.B[1], lz = lc / (g.B[0] * g.B[1]);
+      // the last brick along an axis may be partial: its missing cells would
+      // alias periodic images of another brick's cells
+      if (bx * g.B[0] + lx >= g.nc[0] || by * g.B[1] + ly >= g.nc[1] || bz * g.B[2] + lz >= g.nc[2])
+        continue;
+      const int tc0 = ((lz + 1) * (g.B[1] + 2) + (ly + 1)) * TX + (lx + 1);
+      const int ncell = t.prefix[tc0 + 1] - t.prefix[tc0];
+      const int slot0 = t.src[tc0];
+      const int c0 = slot0 - s0;  // brick index of the cell's first particle
+      const int alo = b0 - c0 > 0 ? b0 - c0 : 0;
+      const int ahi = b1 - c0 < ncell ? b1 - c0 : ncell;
+      for (int a0 = alo; a0 < ahi; a0 += 64) {
+        const int na = ahi - a0 < 64 ? ahi - a0 : 64;
+        const int K = 64 / na;
+        const int ia = lane % na, k = lane / na;
+        const int a = a0 + ia;
+        const bool active = k < K;
+        const int self = t.prefix[tc0] + a;
+        const int s = slot0 + a;  // sorted slot of particle a
+        const int la = c0 + a;    // its index within the brick
+        const bool ok = active && self < kTileCap && la >= b0 && la < b1 && s < s1;
+        uint64_t gm = 0;  // the lanes of particle a
+        for (int kk = 0; kk < K; ++kk) gm |= 1ull << (ia + kk * na);
+        const double xi = ok ? t.x[self] : 0.0, yi = ok ? t.y[self] : 0.0, zi = ok ? t.z[self] : 0.0;
+        uint16_t* __restrict__ mine_stage = stage + (ok ? (la - b0) * 4 * mw : 0);
+        int c = 0;
+        for (int oz = -1; oz <= 1; ++oz) {
+          for (int oy = -1; oy <= 1; ++oy) {
+            const int tcl = tc0 + oz * TXY + oy * TX - 1;
+            for (int tc = tcl; tc < tcl + 3; ++tc) {
+              const int code = t.code[tc];
+              int ue = t.prefix[tc + 1];
+              ue = ue < kTileCap ? ue : kTileCap;
+              const int ub = t.prefix[tc] + k;
+              if (ok) {
+                // lane (a, 0) runs every step that any lane of particle a runs
+                for (int u = ub; u < ue; u += K) {
+                  double d2;
+                  if (code == 21) {  // no image: (1,1,1) in the 2-bit fields
 #pragma clang fp contract(off)
-                const double dx = xi - t.x[u], dy = yi - t.y[u], dz = zi - t.z[u];
-                d2 = (dx * dx + dy * dy) + dz * dz;
-              } else {
-                d2 = exact_d2(xi, yi, zi, t.x[u], t.y[u], t.z[u], Lx, Ly, Lz, hx, hy, hz);
+                    const double dx = xi - t.x[u], dy = yi - t.y[u], dz = zi - t.z[u];
+                    d2 = (dx * dx + dy * dy) + dz * dz;
+                  } else {
+                    d2 = exact_d2(xi, yi, zi, t.x[u], t.y[u], t.z[u], Lx, Ly, Lz, hx, hy, hz);
+                  }
+                  const bool acc = d2 < r2 && u != self;
+                  const uint64_t mine = __ballot(acc) & gm;
+                  if (acc) {
+                    const int rank = c + (int)__builtin_amdgcn_mbcnt_hi(
+                                             (unsigned)(mine >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)mine, 0u));
+                    if (rank < max_nb) mine_stage[rank] = (uint16_t)(u << 3);
+                  }
+                  c += __popcll(mine);
+                }
               }
-              if (d2 < r2 && u != self) {
-                const int m = atomicAdd(&acnt[la], 1);
-                if (m < max_nb)
-                  half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(u << 3);
-              }
+              c = __shfl(c, ia, 64);  // the count of lane (a, 0)
             }
           }
         }
+        if (ok && k == 0) scount[la - b0] = c;
       }
     }
-  }
-  __syncthreads();
-  int most = 0;
-  const int nb = nbrick < kBrickMax ? nbrick : kBrickMax;
-  for (int la = threadIdx.x; la < nb; la += blockDim.x) {
-    const int s = s0 + la;
-    const int count = acnt[la];
-    const int kept = count < max_nb ? count : max_nb;
-    for (int m = kept; m < ((kept + 3) & ~3); ++m)  // pad the last word
-      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(kTileDummy << 3);
-    tl.cnt[s] = kept;
-    if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
-    most = count > most ? count : most;
+    __syncthreads();
+    // write the batch: word w of particle p; consecutive threads take consecutive slots
+    for (int idx = threadIdx.x; idx < np * mw; idx += blockDim.x) {
+      const int p = idx % np, w = idx / np;
+      const int count = scount[p];
+      const int kept = count < max_nb ? count : max_nb;
+      if (4 * w < kept) {
+        const uint16_t* e = stage + p * 4 * mw + 4 * w;
+        uint64_t word = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t v = 4 * w + q < kept ? (uint64_t)e[q] : (uint64_t)(kTileDummy << 3);
+          word |= v << (16 * q);
+        }
+        tl.nbr[(int64_t)w * tl.stride + s0 + b0 + p] = word;
+      }
+    }
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+      const int count = scount[p];
+      tl.cnt[s0 + b0 + p] = count < max_nb ? count : max_nb;
+      if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
+      most = count > most ? count : most;
+    }
+    __syncthreads();  // the next batch reuses stage and scount
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {

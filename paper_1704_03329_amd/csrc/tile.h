@@ -120,6 +120,23 @@ __device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
   __syncthreads();
 }
 
+// slot[u] = sorted slot of tile particle u (u < min(total, kTileCap)).
+// Ends with a barrier.
+__device__ inline void tile_slots(const Grid& g, int total, const TileShared& t, int* slot) {
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int nt = total < kTileCap ? total : kTileCap;
+  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+    int lo = 0, hi = ntc;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (t.prefix[mid] <= u) lo = mid;
+      else hi = mid;
+    }
+    slot[u] = t.src[lo] + (u - t.prefix[lo]);
+  }
+  __syncthreads();
+}
+
 // Tile cell of a brick particle from its cell key.
 __device__ __forceinline__ int home_tile_cell(const Grid& g, int brick, int key) {
   const int local = key - brick * g.V;

@@ -277,6 +277,10 @@ _SIGS_MLP = {
                        ctypes.c_int32),
     "mdpl_scale_velocities": ([ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_double, ctypes.c_void_p],
                               ctypes.c_int32),
+    "mdpl_mlp_run_floats": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mdpl_run_mlp": ([ctypes.c_void_p, ctypes.POINTER(mdpl_mlp_weights), ctypes.c_void_p, ctypes.c_int64]
+                     + [ctypes.c_void_p] * 10 + [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
+    "mdpl_force_error": ([ctypes.c_void_p] * 8, ctypes.c_int32),
 }
 _SIGS.update(_SIGS_MLP)
 
@@ -314,3 +318,20 @@ def mdpl_adam_step(params, grad, m, v, lr, b1, b2, eps, step, w1, w2, w3):
 def mdpl_scale_velocities(vx, vy, vz, factor):
     _check(lib().mdpl_scale_velocities(_ptr(vx), _ptr(vy), _ptr(vz), vx.numel(), float(factor), _stream()),
              "mdpl_scale_velocities")
+
+
+def mdpl_mlp_run_floats(n: int) -> int:
+    out = ctypes.c_int64(0)
+    _check(lib().mdpl_mlp_run_floats(int(n), ctypes.byref(out)), "mdpl_mlp_run_floats")
+    return int(out.value)
+
+
+def mdpl_run_mlp(sim, w: mdpl_mlp_weights, ws, state: dict, nsteps: int, sample_every: int, thermo=None):
+    _check(lib().mdpl_run_mlp(_handle(sim), ctypes.byref(w), _ptr(ws), ws.numel(),
+                              *[_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "ids")],
+                              int(nsteps), int(sample_every), _ptr(thermo)), "mdpl_run_mlp")
+
+
+def mdpl_force_error(sim, fx, fy, fz, gx, gy, gz, out):
+    _check(lib().mdpl_force_error(_handle(sim), _ptr(fx), _ptr(fy), _ptr(fz), _ptr(gx), _ptr(gy), _ptr(gz),
+                                  _ptr(out)), "mdpl_force_error")

@@ -15,7 +15,7 @@ import torch
 import mdinputs
 
 from . import mdpl as C
-from .sim import LJSim, soa
+from .sim import LJSim, boa, soa
 
 NPARAM = 6337
 OFF = {"W1": (0, (64, 32)), "b1": (2048, (64,)), "W2": (2112, (64, 64)), "b2": (6208, (64,)),
@@ -26,7 +26,10 @@ from .mdpl import (  # noqa: E402  (re-exported names of the C entry points)
     mdpl_adam_step,
     mdpl_desc_bwd,
     mdpl_desc_fwd,
+    mdpl_force_error,
     mdpl_mlp_fwd,
+    mdpl_mlp_run_floats,
+    mdpl_run_mlp,
     mdpl_mlp_train_floats,
     mdpl_mlp_train_grad,
     mdpl_mlp_weights,
@@ -200,3 +203,51 @@ def generate_training_set(temperatures=(0.7, 1.0, 1.5), counts=(67, 67, 66), n_c
             raise RuntimeError(f"training MD at T={T} flagged status {status}")
     return {"G": torch.cat(out_G), "e": torch.cat(out_e), "F": torch.cat(out_F), "temp": torch.cat(out_T),
             "snap": torch.cat(out_s)}
+
+
+# ------------------------------------------------------------ MD with the network
+def mlp_md(model: MLPPotential, pos, vel, box, nsteps: int = 500, check_every: int = 50,
+           boa_every: int = 100, boa_rc: float = 1.5, sample_every: int = 10, dt: float = 0.001,
+           reuse_every: int = 10, log=None):
+    """Velocity-Verlet MD with the network as the force field (mdpl_run_mlp),
+    in segments of check_every steps.  After each segment the network's
+    forces are compared with FP64 LJ forces at the same positions
+    (mdpl_force_error); every boa_every steps Q4/Q6 are evaluated with
+    cutoff boa_rc.  Returns dict(state, thermo (rows KE, PE, 0, max disp),
+    checks [(step, rmse, rel)], boa [(step, mean Q4, mean Q6, mean nnb)],
+    force_ms (average network force pass), sim)."""
+    n = int(pos.shape[0])
+    sim = LJSim(n, box, rc=2.5, skin=0.3, dt=dt, reuse_every=reuse_every, precision="fp32", shift="none")
+    ref = LJSim(n, box, rc=2.5, skin=0.3, precision="fp64", shift="none")
+    st = sim.new_state(pos, vel)
+    ws = torch.empty(mdpl_mlp_run_floats(n), dtype=torch.float32, device=sim.device)
+    err = torch.empty(2, dtype=torch.float64, device=sim.device)
+    w = model.weights()
+    rows_per = check_every // sample_every + 1
+    thermo, checks, boas = [], [], []
+    from . import mdpl as C
+
+    C.mdpl_set_timing(sim.handle, True)
+    C.mdpl_kernel_time(sim.handle, 0)
+    C.mdpl_kernel_time(sim.handle, 1)
+    for seg in range(nsteps // check_every):
+        th = torch.empty((rows_per, 4), dtype=torch.float64, device=sim.device)
+        mdpl_run_mlp(sim, w, ws, st, check_every, sample_every, th)
+        step = (seg + 1) * check_every
+        thermo.append(th if seg == 0 else th[1:])
+        ref.build(st["x"], st["y"], st["z"])
+        gx, gy, gz, _, _ = ref.forces(st["x"], st["y"], st["z"])
+        mdpl_force_error(ref, st["fx"], st["fy"], st["fz"], gx, gy, gz, err)
+        e = err.cpu().numpy()
+        checks.append((step, float(np.sqrt(e[0] / (3 * n))), float(np.sqrt(e[0] / e[1]))))
+        if boa_every and step % boa_every == 0:
+            q = boa(st["x"], st["y"], st["z"], box, boa_rc)
+            boas.append((step, float(q["q4"].double().mean().item()), float(q["q6"].double().mean().item()),
+                         float(q["nnb"].double().mean().item())))
+        if log:
+            log(f"step {step}: force RMSE vs LJ {checks[-1][1]:.4f} (rel {checks[-1][2]:.4f})")
+    p_ms, p_n = C.mdpl_kernel_time(sim.handle, 0)
+    e_ms, e_n = C.mdpl_kernel_time(sim.handle, 1)
+    C.mdpl_set_timing(sim.handle, False)
+    return {"state": st, "thermo": torch.cat(thermo), "checks": checks, "boa": boas,
+            "force_ms": (p_ms + e_ms) / max(p_n + e_n, 1), "sim": sim}

@@ -1,0 +1,93 @@
+"""MD with the learned potential as the force field at full size:
+N = 8,000,000 (200^3 simple-cubic lattice, rho 0.8442, T* = 1, seed 5),
+500 velocity-Verlet steps (dt 0.001, list rebuild every 10 steps), the
+network's forces checked against FP64 LJ every 50 steps, Q4/Q6 every 100
+steps with cutoff 1.5, FP64 energy of the network Hamiltonian.
+
+Trajectories are chaotic, so they are not compared step by step.  What is
+checked: at the last step the network forces of sampled atoms equal the FP64
+oracle (descriptors + network with the same bf16-rounded weights) evaluated
+on the local cluster within 5.2 of each sampled atom (relative L2 <= 2e-2,
+the bar of the small-size parity test); no flags; energy per atom conserved
+to 1e-3; the LJ-check error stays below 25% of the LJ force RMS (the
+network is trained on liquid snapshots at T* 0.7-1.5 and starts here from a
+lattice); Q4/Q6 are in [0, 1] and the lattice melts (mean Q6 below the
+simple-cubic 0.354)."""
+import numpy as np
+import pytest
+import torch
+
+import mdinputs
+from conftest import gpu_device
+from oracle import descriptor as OD
+from oracle import lj as olj
+from oracle import mlp as OM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trained():
+    from paper_1704_03329_amd import potential as P
+
+    gpu_device()
+    data = P.generate_training_set()
+    m = P.MLPPotential(seed=11)
+    m.set_standardisation(data["G"], data["e"])
+    m.train(data["G"], data["e"], steps=6000, batch=4096, lr=3e-3, lr_final=1e-4)
+    torch.cuda.synchronize()
+    return m
+
+
+def _oracle_force(m, pos, box, centre):
+    """Oracle network force on one atom from the cluster within 5.2 of it."""
+    idx = olj.local_subset(pos, box, centre, 5.2)
+    rel = pos[idx] - pos[centre]
+    rel -= box * np.round(rel / box)
+    c = int(np.nonzero(idx == centre)[0][0])
+    big = np.array([1e6, 1e6, 1e6])  # an open cluster: no periodic image within reach
+    cluster = rel
+    d = np.sqrt(np.sum(rel * rel, axis=1))
+    rows = np.nonzero(d < OD.RC)[0]  # the centre and its neighbours
+    G, table, grads = OD.descriptors(cluster, big, rows=rows, with_grad=True)
+    p = m.host_params()
+    _, dEdG = OM.energy_and_feature_grad(p, G, m.mu.double().cpu().numpy(), m.sd.double().cpu().numpy(),
+                                         m.e_mean, m.e_sd)
+    F = OD.forces_from_feature_grad(cluster.shape[0], rows, table, grads, dEdG)
+    return F[c]
+
+
+def test_mlp_md_8m(trained):
+    from paper_1704_03329_amd import potential as P
+
+    d = mdinputs.lj_fluid(200, temperature=1.0, seed=5)
+    n = d["pos"].shape[0]
+    box = d["box"]
+    assert n == 8_000_000
+    out = P.mlp_md(trained, torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]), box, nsteps=500,
+                   log=lambda s: print(s, flush=True))
+    st, sim = out["state"], out["sim"]
+    status, flags, _ = sim.check(raise_on_error=False)
+    assert status == 0, flags
+    th = out["thermo"].cpu().numpy()
+    H = th[:, 0] + th[:, 1]
+    drift = float(np.max(np.abs(H - H[0])) / n)
+    print(f"network force pass {out['force_ms']:.2f} ms; energy drift per atom {drift:.3e}; "
+          f"checks {out['checks']}; boa {out['boa']}")
+    assert np.all(np.isfinite(th))
+    assert drift <= 1e-3
+    # LJ check: error relative to the LJ force norm
+    for step, rmse, rel in out["checks"]:
+        assert np.isfinite(rmse) and rel < 0.25, (step, rel)
+    assert [b[0] for b in out["boa"]] == [100, 200, 300, 400, 500]
+    for _, q4, q6, nnb in out["boa"]:
+        assert 0.0 <= q4 <= 1.0 and 0.0 <= q6 <= 1.0 and nnb > 0
+    assert out["boa"][-1][2] < 0.354
+    # sampled parity with the oracle at the final positions
+    pos = torch.stack([st["x"], st["y"], st["z"]], 1).cpu().numpy()
+    F = torch.stack([st["fx"], st["fy"], st["fz"]], 1).double().cpu().numpy()
+    pos = pos - box * np.floor(pos / box)
+    sample = np.random.Generator(np.random.PCG64(17)).choice(n, 6, replace=False)
+    ref = np.stack([_oracle_force(trained, pos, box, int(a)) for a in sample])
+    got = F[sample]
+    assert np.linalg.norm(got - ref) <= 2e-2 * np.linalg.norm(ref)
