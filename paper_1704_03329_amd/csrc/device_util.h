@@ -21,15 +21,13 @@ __device__ __forceinline__ double exact_d2(double xi, double yi, double zi, doub
                                            double zj, double Lx, double Ly, double Lz, double hx,
                                            double hy, double hz) {
 #pragma clang fp contract(off)
+  // both wraps are formed and selected, so no lane branches
   double dx = xi - xj;
-  if (dx > hx) dx = dx - Lx;
-  else if (dx < -hx) dx = dx + Lx;
+  dx = dx > hx ? dx - Lx : (dx < -hx ? dx + Lx : dx);
   double dy = yi - yj;
-  if (dy > hy) dy = dy - Ly;
-  else if (dy < -hy) dy = dy + Ly;
+  dy = dy > hy ? dy - Ly : (dy < -hy ? dy + Ly : dy);
   double dz = zi - zj;
-  if (dz > hz) dz = dz - Lz;
-  else if (dz < -hz) dz = dz + Lz;
+  dz = dz > hz ? dz - Lz : (dz < -hz ? dz + Lz : dz);
   return (dx * dx + dy * dy) + dz * dz;
 }
 

@@ -11,7 +11,7 @@
 // Two builders:
 //  * the LJ list: one workgroup per brick stages its tile (stored positions,
 //    no images) in LDS, one wave per home cell tests the 27 tile cells of its
-//    stencil; entries are 16-bit tile indices, column-major, so the force
+//    stencil; entries are 16-bit tile byte offsets, column-major, so the force
 //    pass reads one coalesced word per four neighbours;
 //  * the analysis list (bond order / CNA): one thread per particle walks the
 //    9 rows of 3 consecutive cells in global memory, entries are sorted-slot
@@ -25,29 +25,90 @@ namespace mdpl {
 // ------------------------------------------------------------------ LJ list
 // One wave per home cell at a time.  The cell's particles (na <= 64 per
 // pass) are spread over the 64 lanes as na x K (K = 64 / na): lane
-// (a, k) = a + na k tests particle a against candidates k, k+K, k+2K, ...
-// of every stencil cell, so all lanes walk the same 27 cells together and
-// lanes with equal k read the same tile slot.
+// (a, k) tests particle a against candidates k, k+K, k+2K, ... of each
+// stencil row (three consecutive tile cells, one contiguous index range),
+// so all lanes walk the same 9 rows together and lanes with equal k read
+// the same tile slot.  Accepted neighbours get their rank from a
+// per-particle LDS counter and are stored as 16-bit halves of the list
+// words; a final pass pads the last word and writes the counts.
 //
-// Ranks come from wave ballots, not atomics: in each step the accepted
-// lanes of particle a are counted below the lane (mbcnt) and in total
-// (popcount), so a list is ordered by candidate and is the same on every
-// run.  Lists are staged in LDS for a batch of the brick's particles and
-// written out as whole 64-bit words, consecutive slots in consecutive
-// words (coalesced), the last word padded with the dummy entry.
-//
-// Cells without a periodic image (code 0) use the stored positions directly,
-// which is exactly the definition's arithmetic; image cells fall back to the
-// exact conditional minimum image.
-constexpr int kStageEntries = 36864;  // 16-bit entries staged per workgroup (72 KB)
+// Rows without a periodic image (code 21 in all three cells) use the stored
+// positions directly, which is exactly the definition's arithmetic; image
+// cells apply their known shift (scan_range).
+// Separation of a tile candidate under the three ways of forming the
+// definition's minimum image:
+//   PLAIN: the cell is no periodic image (the wrap never applies);
+//   SHIFT: the cell is the image shifted by (sx, sy, sz) boxes and the grid
+//          has >= 5 cells per axis, so the wrap applies exactly on the
+//          shifted axes (|xi - xj| > L/2 there, < L/2 elsewhere):
+//          dx = fl(fl(xi - xj) - sx L), with sx L = 0 an exact no-op;
+//   EXACT: the conditional wrap itself (small grids).
+enum { kPlain = 0, kShift = 1, kExact = 2 };
+
+struct RowScan {
+  double xi, yi, zi, r2;
+  double sLx, sLy, sLz;      // SHIFT offsets
+  double Lx, Ly, Lz, hx, hy, hz;
+  int self, K, max_nb;
+  int* cnt;                  // the particle's LDS counter
+  uint16_t* base;            // its list: entry m at base[(m >> 2) * stride4 + (m & 3)]
+  uint32_t stride4;
+};
+
+// Candidates u = ub, ub + K, ... < ue (one contiguous range of tile
+// indices), UNROLL at a time so that their LDS loads overlap; slots past the
+// end read the far-away dummy.  One LDS atomic reserves the ranks of all
+// accepted candidates of a step.
+template <int MODE, int UNROLL>
+__device__ __forceinline__ void scan_range(const TileShared& t, int ub, int ue, const RowScan& q) {
+#pragma clang fp contract(off)
+  for (int u0 = ub; u0 < ue; u0 += UNROLL * q.K) {
+    int uu[UNROLL];
+    bool acc[UNROLL];
+    int na = 0;
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) {
+      const int u = u0 + j * q.K;
+      uu[j] = u < ue ? u : kTileDummy;
+    }
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) {
+      const double xj = t.x[uu[j]], yj = t.y[uu[j]], zj = t.z[uu[j]];
+      double d2;
+      if (MODE == kExact) {
+        d2 = exact_d2(q.xi, q.yi, q.zi, xj, yj, zj, q.Lx, q.Ly, q.Lz, q.hx, q.hy, q.hz);
+      } else {
+        double dx = q.xi - xj, dy = q.yi - yj, dz = q.zi - zj;
+        if (MODE == kShift) {
+          dx = dx - q.sLx;
+          dy = dy - q.sLy;
+          dz = dz - q.sLz;
+        }
+        d2 = (dx * dx + dy * dy) + dz * dz;
+      }
+      acc[j] = d2 < q.r2 && uu[j] != q.self;
+      na += acc[j] ? 1 : 0;
+    }
+    if (na) {
+      uint32_t m = (uint32_t)atomicAdd(q.cnt, na);
+#pragma unroll
+      for (int j = 0; j < UNROLL; ++j) {
+        if (acc[j]) {
+          if (m < (uint32_t)q.max_nb)
+            q.base[(uint64_t)(m >> 2) * q.stride4 + (m & 3u)] = (uint16_t)(uu[j] << 3);
+          ++m;
+        }
+      }
+    }
+  }
+}
 
 __global__ __launch_bounds__(1024) void k_build_tile_nlist(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
     TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
   __shared__ TileShared t;
-  __shared__ uint16_t stage[kStageEntries];
-  __shared__ int scount[kBrickMax];
+  __shared__ int acnt[kBrickMax];
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
@@ -55,113 +116,97 @@ __global__ __launch_bounds__(1024) void k_build_tile_nlist(
   const int nbrick = s1 - s0;
   if (threadIdx.x == 0 && (total > kTileCap || nbrick > kBrickMax))
     atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
+  for (int a = threadIdx.x; a < kBrickMax; a += blockDim.x) acnt[a] = 0;
   tile_load<false>(g, x, y, z, total, t);  // ends with a barrier
   const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
   const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+  const bool shift_ok = g.nc[0] >= 5 && g.nc[1] >= 5 && g.nc[2] >= 5;
   const int TX = g.B[0] + 2, TXY = TX * (g.B[1] + 2);
   const int max_nb = tl.max_nb;
-  const int mw = (max_nb + 3) >> 2;  // words per particle
-  int per = kStageEntries / (4 * mw);
-  per = per < kBrickMax ? per : kBrickMax;
-  const int nb = nbrick < kBrickMax ? nbrick : kBrickMax;
+  uint16_t* __restrict__ half = (uint16_t*)tl.nbr;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   int bx, by, bz;
   brick_coords(g, brick, bx, by, bz);
-  int most = 0;
-  for (int b0 = 0; b0 < nb; b0 += per) {
-    const int b1 = b0 + per < nb ? b0 + per : nb;
-    const int np = b1 - b0;
-    for (int p = threadIdx.x; p < np; p += blockDim.x) scount[p] = 0;
-    __syncthreads();
-    for (int lc = wave; lc < g.V; lc += nwaves) {
-      const int lx = lc % g.B[0], ly = (lc / g.B[0]) % g.B[1], lz = lc / (g.B[0] * g.B[1]);
-      // the last brick along an axis may be partial: its missing cells would
-      // alias periodic images of another brick's cells
-      if (bx * g.B[0] + lx >= g.nc[0] || by * g.B[1] + ly >= g.nc[1] || bz * g.B[2] + lz >= g.nc[2])
-        continue;
-      const int tc0 = ((lz + 1) * (g.B[1] + 2) + (ly + 1)) * TX + (lx + 1);
-      const int ncell = t.prefix[tc0 + 1] - t.prefix[tc0];
-      const int slot0 = t.src[tc0];
-      const int c0 = slot0 - s0;  // brick index of the cell's first particle
-      const int alo = b0 - c0 > 0 ? b0 - c0 : 0;
-      const int ahi = b1 - c0 < ncell ? b1 - c0 : ncell;
-      for (int a0 = alo; a0 < ahi; a0 += 64) {
-        const int na = ahi - a0 < 64 ? ahi - a0 : 64;
-        const int K = 64 / na;
-        const int ia = lane % na, k = lane / na;
-        const int a = a0 + ia;
-        const bool active = k < K;
-        const int self = t.prefix[tc0] + a;
-        const int s = slot0 + a;  // sorted slot of particle a
-        const int la = c0 + a;    // its index within the brick
-        const bool ok = active && self < kTileCap && la >= b0 && la < b1 && s < s1;
-        uint64_t gm = 0;  // the lanes of particle a
-        for (int kk = 0; kk < K; ++kk) gm |= 1ull << (ia + kk * na);
-        const double xi = ok ? t.x[self] : 0.0, yi = ok ? t.y[self] : 0.0, zi = ok ? t.z[self] : 0.0;
-        uint16_t* __restrict__ mine_stage = stage + (ok ? (la - b0) * 4 * mw : 0);
-        int c = 0;
-        for (int oz = -1; oz <= 1; ++oz) {
-          for (int oy = -1; oy <= 1; ++oy) {
-            const int tcl = tc0 + oz * TXY + oy * TX - 1;
-            for (int tc = tcl; tc < tcl + 3; ++tc) {
-              const int code = t.code[tc];
-              int ue = t.prefix[tc + 1];
-              ue = ue < kTileCap ? ue : kTileCap;
-              const int ub = t.prefix[tc] + k;
-              if (ok) {
-                // lane (a, 0) runs every step that any lane of particle a runs
-                for (int u = ub; u < ue; u += K) {
-                  double d2;
-                  if (code == 21) {  // no image: (1,1,1) in the 2-bit fields
-#pragma clang fp contract(off)
-                    const double dx = xi - t.x[u], dy = yi - t.y[u], dz = zi - t.z[u];
-                    d2 = (dx * dx + dy * dy) + dz * dz;
-                  } else {
-                    d2 = exact_d2(xi, yi, zi, t.x[u], t.y[u], t.z[u], Lx, Ly, Lz, hx, hy, hz);
-                  }
-                  const bool acc = d2 < r2 && u != self;
-                  const uint64_t mine = __ballot(acc) & gm;
-                  if (acc) {
-                    const int rank = c + (int)__builtin_amdgcn_mbcnt_hi(
-                                             (unsigned)(mine >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((unsigned)mine, 0u));
-                    if (rank < max_nb) mine_stage[rank] = (uint16_t)(u << 3);
-                  }
-                  c += __popcll(mine);
-                }
-              }
-              c = __shfl(c, ia, 64);  // the count of lane (a, 0)
+  for (int lc = wave; lc < g.V; lc += nwaves) {
+    const int lx = lc % g.B[0], ly = (lc / g.B[0]) % g.B[1], lz = lc / (g.B[0] * g.B[1]);
+    // the last brick along an axis may be partial: its missing cells would
+    // alias periodic images of another brick's cells
+    if (bx * g.B[0] + lx >= g.nc[0] || by * g.B[1] + ly >= g.nc[1] || bz * g.B[2] + lz >= g.nc[2])
+      continue;
+    const int tc0 = ((lz + 1) * (g.B[1] + 2) + (ly + 1)) * TX + (lx + 1);
+    const int ncell = t.prefix[tc0 + 1] - t.prefix[tc0];
+    const int slot0 = t.src[tc0];
+    for (int a0 = 0; a0 < ncell; a0 += 64) {
+      const int na = ncell - a0 < 64 ? ncell - a0 : 64;
+      const int K = 64 / na;
+      const int a = a0 + lane % na, k = lane / na;
+      const bool active = k < K;
+      const int self = t.prefix[tc0] + a;
+      const int s = slot0 + a;          // sorted slot of particle a
+      const int la = s - s0;            // its index within the brick
+      const bool ok = active && self < kTileCap && la >= 0 && la < kBrickMax && s < s1;
+      RowScan q;
+      q.xi = ok ? t.x[self] : 0.0;
+      q.yi = ok ? t.y[self] : 0.0;
+      q.zi = ok ? t.z[self] : 0.0;
+      q.r2 = r2;
+      q.Lx = Lx;
+      q.Ly = Ly;
+      q.Lz = Lz;
+      q.hx = hx;
+      q.hy = hy;
+      q.hz = hz;
+      q.self = self;
+      q.K = K;
+      q.max_nb = max_nb;
+      q.cnt = &acnt[ok ? la : 0];
+      q.base = half + (int64_t)(ok ? s : 0) * 4;
+      q.stride4 = (uint32_t)(tl.stride * 4);
+      for (int oz = -1; oz <= 1; ++oz) {
+        for (int oy = -1; oy <= 1; ++oy) {
+          // a stencil row: three consecutive tile cells, one contiguous index range
+          const int tcl = tc0 + oz * TXY + oy * TX - 1;
+          const int c0 = t.code[tcl], c1 = t.code[tcl + 1], c2 = t.code[tcl + 2];
+          if (!ok) continue;
+          if (c0 == 21 && c1 == 21 && c2 == 21) {
+            int ue = t.prefix[tcl + 3];
+            ue = ue < kTileCap ? ue : kTileCap;
+            scan_range<kPlain, 4>(t, t.prefix[tcl] + k, ue, q);
+            continue;
+          }
+          for (int tc = tcl; tc < tcl + 3; ++tc) {
+            const int code = t.code[tc];
+            int ue = t.prefix[tc + 1];
+            ue = ue < kTileCap ? ue : kTileCap;
+            const int ub = t.prefix[tc] + k;
+            if (code == 21) {
+              scan_range<kPlain, 4>(t, ub, ue, q);
+            } else if (shift_ok) {
+              q.sLx = (double)((code & 3) - 1) * Lx;
+              q.sLy = (double)(((code >> 2) & 3) - 1) * Ly;
+              q.sLz = (double)(((code >> 4) & 3) - 1) * Lz;
+              scan_range<kShift, 4>(t, ub, ue, q);
+            } else {
+              scan_range<kExact, 4>(t, ub, ue, q);
             }
           }
         }
-        if (ok && k == 0) scount[la - b0] = c;
       }
     }
-    __syncthreads();
-    // write the batch: word w of particle p; consecutive threads take consecutive slots
-    for (int idx = threadIdx.x; idx < np * mw; idx += blockDim.x) {
-      const int p = idx % np, w = idx / np;
-      const int count = scount[p];
-      const int kept = count < max_nb ? count : max_nb;
-      if (4 * w < kept) {
-        const uint16_t* e = stage + p * 4 * mw + 4 * w;
-        uint64_t word = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint64_t v = 4 * w + q < kept ? (uint64_t)e[q] : (uint64_t)(kTileDummy << 3);
-          word |= v << (16 * q);
-        }
-        tl.nbr[(int64_t)w * tl.stride + s0 + b0 + p] = word;
-      }
-    }
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-      const int count = scount[p];
-      tl.cnt[s0 + b0 + p] = count < max_nb ? count : max_nb;
-      if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
-      most = count > most ? count : most;
-    }
-    __syncthreads();  // the next batch reuses stage and scount
+  }
+  __syncthreads();
+  int most = 0;
+  const int nb = nbrick < kBrickMax ? nbrick : kBrickMax;
+  for (int la = threadIdx.x; la < nb; la += blockDim.x) {
+    const int s = s0 + la;
+    const int count = acnt[la];
+    const int kept = count < max_nb ? count : max_nb;
+    for (int m = kept; m < ((kept + 3) & ~3); ++m)  // pad the last word
+      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(kTileDummy << 3);
+    tl.cnt[s] = kept;
+    if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
+    most = count > most ? count : most;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
