@@ -191,6 +191,45 @@ def mlp_report(args):
     }
 
 
+def analysis_report():
+    """Bond order (Q4, Q6) and CNA on the structure-analysis workload: 50
+    FCC/HCP/BCC grains, N ~ 4e6, rho 1, jitter 0.05 d, seed 3, cutoff 1.2684 d."""
+    import numpy as np
+    import torch
+
+    import mdinputs
+    from paper_1704_03329_amd import mdpl as C
+    from paper_1704_03329_amd.sim import soa
+
+    log("analysis: generating the 4e6-atom polycrystal")
+    pc = mdinputs.polycrystal(4_000_000, 50, seed=3)
+    box, rc = pc["box"], 1.2684 * pc["d"]
+    x, y, z = soa(torch.from_numpy(pc["pos"]).cuda())
+    n = x.numel()
+    dev = x.device
+    ws_b = torch.empty(C.mdpl_analysis_workspace_bytes(n, box, rc, 1), dtype=torch.uint8, device=dev)
+    ws_c = torch.empty(C.mdpl_analysis_workspace_bytes(n, box, rc, 16), dtype=torch.uint8, device=dev)
+    q4 = torch.empty(n, dtype=torch.float32, device=dev)
+    q6 = torch.empty_like(q4)
+    nnb = torch.empty(n, dtype=torch.int32, device=dev)
+    trip = torch.empty((n, 16), dtype=torch.int32, device=dev)
+    label = torch.empty(n, dtype=torch.uint8, device=dev)
+    t_boa = event_time(lambda: C.mdpl_boa(x, y, z, box, rc, q4, None, q6, nnb, ws_b), 5)
+    t_cna = event_time(lambda: C.mdpl_cna(x, y, z, box, rc, 16, trip, nnb, label, ws_c), 5)
+    frac = np.bincount(label.cpu().numpy(), minlength=4) / n
+    log(f"analysis: BOA {t_boa * 1e3:.2f} ms, CNA {t_cna * 1e3:.2f} ms")
+    return {
+        "workload": f"50 FCC/HCP/BCC grains, N={n}, rho 1.0, jitter 0.05 d, seed 3, cutoff {rc:.4f} "
+                    "(neighbour list, bond order and CNA each included)",
+        "n_atoms": n,
+        "boa_ms": t_boa * 1e3,
+        "cna_ms": t_cna * 1e3,
+        "boa_atoms_per_s": n / t_boa,
+        "cna_atoms_per_s": n / t_cna,
+        "label_fractions": {k: float(v) for k, v in zip(("other", "fcc", "hcp", "bcc"), frac)},
+    }
+
+
 def lj32_forces(sim, x, y, z, out):
     from paper_1704_03329_amd import mdpl as C
 
@@ -206,6 +245,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=192)
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--no-analysis", action="store_true")
     ap.add_argument("--mlp-steps", type=int, default=6000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one elementwise copy of this many MiB (HBM counter calibration)")
@@ -321,6 +361,8 @@ def main():
     }
     if not args.no_mlp:
         out["mlp_vs_lj"] = mlp_report(args)
+    if not args.no_analysis:
+        out["analysis"] = analysis_report()
     if not args.no_cpu_baseline:
         log(f"oracle CPU baseline on {args.cpu_rows} atoms")
         out["cpu_baseline"] = cpu_baseline(d["pos"], box, args.cpu_rows)

@@ -40,6 +40,30 @@ constexpr int kNFeat = 24;
 constexpr int kNMom = 25;
 constexpr float kEtaR = 41.32231404958678f;  // 1 / (2 * 0.11^2)
 
+// exp(x) on the hardware base-2 exponential
+__device__ __forceinline__ float exp_hw(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// e_k = exp(-eta_r (r - R_k)^2), k < 16.  With eta_r = 1/(2 * 0.11^2) and
+// R_{k+1} = R_k + 0.11 the ratio e_{k+1}/e_k = rho_k = exp((r - R_k)/0.11 - 1/2)
+// and rho_{k+1} = rho_k / e, so three terms follow from every fourth by
+// multiplication; the anchors are exact exponentials (a chain from k = 0
+// would underflow for r far from R_0).
+__device__ __forceinline__ void radial_basis(float r, float e[kNRad]) {
+  const float inv_e = 0.36787944117144233f;
+  float rho = exp_hw((r - 0.85f) * (1.0f / 0.11f) - 0.5f);  // rho_0
+#pragma unroll
+  for (int a = 0; a < kNRad; a += 4) {
+    const float d = r - (0.85f + 0.11f * (float)a);
+    e[a] = exp_hw(-kEtaR * d * d);
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      e[a + j] = e[a + j - 1] * rho;
+      rho *= inv_e;
+    }
+    rho *= inv_e;  // rho_{a+4}
+  }
+}
+
 // 2 (l-m)!/(l+m)! (1 for m = 0), indexed l(l+1)/2 + m
 __device__ __forceinline__ float omega(int idx) {
   const float t[15] = {1.0f,
@@ -115,7 +139,7 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
   tile_load<true>(g, x, y, z, total, t);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const double rc2 = (double)rc * (double)rc;
-  const float pi_rc = 3.14159265358979f / rc;
+  const float half_rev = 0.5f / rc;  // revolutions per unit r of cos(pi r / rc)
   for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
     const double xi = x[s], yi = y[s], zi = z[s];
     float G[kNRad];
@@ -139,17 +163,18 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
         const float r = sqrtf((float)d2);
         const float ir = 1.0f / r;
         const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
-        const float fc = 0.5f * (cosf(pi_rc * r) + 1.0f);
+        const float fc = 0.5f * (__builtin_amdgcn_cosf(r * half_rev) + 1.0f);  // cos(pi r / rc)
+        float eb[kNRad];
+        radial_basis(r, eb);
 #pragma unroll
-        for (int k = 0; k < kNRad; ++k) {
-          const float d = r - (0.85f + 0.11f * (float)k);
-          G[k] += expf(-kEtaR * d * d) * fc;
-        }
+        for (int k = 0; k < kNRad; ++k) G[k] += eb[k] * fc;
         float P[15], c[5], sn[5];
         legendre_d(uz, P);
         cpow(ux, uy, c, sn);
-        const float w0 = expf(-0.5f * r * r) * fc;
-        const float w1 = expf(-2.0f * r * r) * fc;
+        const float g0 = exp_hw(-0.5f * r * r);
+        const float g1 = (g0 * g0) * (g0 * g0);  // exp(-2 r^2)
+        const float w0 = g0 * fc;
+        const float w1 = g1 * fc;
         diag[0] += w0 * w0;
         diag[1] += w1 * w1;
 #pragma unroll
@@ -251,17 +276,20 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
   legendre_d(uz, P);
   cpow(ux, uy, c, sn);
   float radial = 0.0f;  // scalar multiplying uh
+  float eb[kNRad];
+  radial_basis(r, eb);
 #pragma unroll
   for (int k = 0; k < kNRad; ++k) {
     const float d = r - (0.85f + 0.11f * (float)k);
-    const float e = expf(-kEtaR * d * d);
-    radial += K[52 + k] * e * (-2.0f * kEtaR * d * fc + dfc);
+    radial += K[52 + k] * eb[k] * (-2.0f * kEtaR * d * fc + dfc);
   }
+  const float g0 = exp_hw(-0.5f * r * r);
+  const float gsq = g0 * g0;
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const float eta = e ? 2.0f : 0.5f;
-    const float ex = expf(-eta * r * r);
+    const float ex = e ? gsq * gsq : g0;  // exp(-eta r^2)
     const float w = ex * fc;
     const float dw = ex * (-2.0f * eta * r * fc + dfc);
     float phi = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
@@ -311,6 +339,7 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const double rc2 = (double)rc * (double)rc;
   const float pi_rc = 3.14159265358979f / rc;
+  const float half_rev = 0.5f / rc;
   for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
     const double xi = x[s], yi = y[s], zi = z[s];
     const int64_t oi = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
@@ -331,9 +360,8 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
         const float r = sqrtf((float)d2);
         const float ir = 1.0f / r;
         const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
-        const float ang = pi_rc * r;
-        const float fc = 0.5f * (cosf(ang) + 1.0f);
-        const float dfc = -0.5f * pi_rc * sinf(ang);
+        const float fc = 0.5f * (__builtin_amdgcn_cosf(r * half_rev) + 1.0f);
+        const float dfc = -0.5f * pi_rc * __builtin_amdgcn_sinf(r * half_rev);
         const int sj = slot_of[u];
         const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
         // Both terms of the pair in one evaluation: the basis has parity

@@ -88,14 +88,16 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
           const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
           const bool in = d2 < c.rc2;
           MT inv;
-          if constexpr (sizeof(MT) == 4)
-            inv = __builtin_amdgcn_rcpf((float)d2);
-          else
+          if constexpr (sizeof(MT) == 4) {
+            // outside the cutoff the reciprocal of FLT_MAX drives the factor to zero
+            inv = __builtin_amdgcn_rcpf(in ? (float)d2 : 3.0e38f);
+          } else {
             inv = 1.0 / d2;
+          }
           const MT s2 = sig2 * inv;
           const MT s6 = s2 * s2 * s2;
           MT gg = inv * s6 * (c48 * s6 - c24);
-          gg = in ? gg : (MT)0;
+          if constexpr (sizeof(MT) != 4) gg = in ? gg : (MT)0;
           g = (double)gg;
         }
         ax = __builtin_fma(g, dx, ax);
