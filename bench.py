@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n-side", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=192)
+    ap.add_argument("--cpu-rows", type=int, default=1024)
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
     ap.add_argument("--mlp-steps", type=int, default=6000)

@@ -218,7 +218,10 @@ mdpl_status mdpl_desc_fwd(mdpl_sim* sim, const double* x, const double* y, const
 
 /* Forces F_i = -dE/dr_i of E = sum_i E_i(G_i), from dEdG (n x 24, dE_i/dG_i)
  * and mom of mdpl_desc_fwd at the same positions.  coef: n x 68 float
- * scratch (caller-owned).  fx, fy, fz: float, caller order. */
+ * scratch (caller-owned).  fx, fy, fz: float, caller order, overwritten.
+ * The pair terms are summed with FP32 atomics, so the last bits of the
+ * forces may differ between runs (the sum of all forces stays zero to
+ * rounding). */
 mdpl_status mdpl_desc_bwd(mdpl_sim* sim, const double* x, const double* y, const double* z,
                           const float* dEdG, const float* mom, float* coef, float* fx, float* fy,
                           float* fz);

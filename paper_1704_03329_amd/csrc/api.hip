@@ -643,7 +643,7 @@ mdpl_status mdpl_desc_bwd(mdpl_sim* s, const double* x, const double* y, const d
   HIP_TRY(desc_adjoint(dEdG, mom, s->n, coef, s->st));
   HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   HIP_TRY(desc_backward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm,
-                        coef, fx, fy, fz, s->st));
+                        coef, s->n, fx, fy, fz, s->st));
   return MDPL_OK;
 }
 
@@ -755,7 +755,7 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
                     HIP_TRY(mlp_eval(a, s->st));
                     HIP_TRY(desc_adjoint(dG, mom, n, coef, s->st));
                     HIP_TRY(desc_backward(cur.x, cur.y, cur.z, s->cell_start, s->g, s->tl, rc,
-                                          nullptr, coef, (float*)cur.fx, (float*)cur.fy,
+                                          nullptr, coef, n, (float*)cur.fx, (float*)cur.fy,
                                           (float*)cur.fz, s->st));
                     if (e1) {
                       HIP_TRY(hipEventRecord(e1, s->st));

@@ -324,18 +324,41 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
 }
 
 // ------------------------------------------------------------- backward
+// The term of pair (i, j) that involves centre i's coefficients,
+// g_ij = dE_i/du_ij, enters F_i with + and F_j with - (F_a = sum_j dE_a/du_aj
+// - dE_j/du_ja), so each thread needs only its own K_i: it adds g_ij to its
+// particle and subtracts it from the neighbour's LDS accumulator; the block
+// then adds its accumulators to the outputs with global atomics (the output
+// is zeroed first).  FP32 atomics make the last bits of the forces depend on
+// the order in which blocks and waves land.
+__global__ void k_zero3(float* __restrict__ a, float* __restrict__ b, float* __restrict__ c,
+                        int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    a[i] = 0.0f;
+    b[i] = 0.0f;
+    c[i] = 0.0f;
+  }
+}
+
 __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    const double* __restrict__ z,
                                                    const int32_t* __restrict__ cs, Grid g,
                                                    TileList tl, float rc, DescIO io) {
   __shared__ TileShared t;
-  __shared__ int slot_of[kTileMax];
+  __shared__ float acc[3][kTileMax];
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
-  tile_load<true>(g, x, y, z, total, t);
-  tile_slots(g, total, t, slot_of);
+  const int nt = total < kTileCap ? total : kTileCap;
+  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+    acc[0][u] = 0.0f;
+    acc[1][u] = 0.0f;
+    acc[2][u] = 0.0f;
+  }
+  tile_load<true>(g, x, y, z, total, t);  // ends with a barrier
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const double rc2 = (double)rc * (double)rc;
   const float pi_rc = 3.14159265358979f / rc;
@@ -353,7 +376,7 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
       const uint64_t word = col[(int64_t)gi * tl.stride];
       for (int q = 0; q < 4; ++q) {
         const int u = (int)((word >> (16 * q)) & 0xffff) >> 3;
-        if (u >= total || u >= kTileCap) continue;  // padding slot
+        if (u >= nt) continue;  // padding slot
         const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (!(d2 < rc2)) continue;
@@ -362,24 +385,36 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
         const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
         const float fc = 0.5f * (__builtin_amdgcn_cosf(r * half_rev) + 1.0f);
         const float dfc = -0.5f * pi_rc * __builtin_amdgcn_sinf(r * half_rev);
-        const int sj = slot_of[u];
-        const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
-        // Both terms of the pair in one evaluation: the basis has parity
-        // (-1)^l, so -dE_j/du_ji equals dE/du_ij of a centre whose odd-l
-        // coefficients are those of j with the sign flipped (linear in K).
-        float K[68];
-#pragma unroll
-        for (int k = 0; k < 68; ++k) {
-          const int l = k < 50 ? (k % kNMom < 1 ? 0 : (k % kNMom < 4 ? 1 : (k % kNMom < 9 ? 2 : (k % kNMom < 16 ? 3 : 4)))) : 0;
-          const float kj = io.coef[oj * 68 + k];
-          K[k] = Ki[k] + ((l & 1) ? -kj : kj);
-        }
-        pair_grad(K, r, ux, uy, uz, fc, dfc, fx, fy, fz);
+        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+        pair_grad(Ki, r, ux, uy, uz, fc, dfc, gx, gy, gz);
+        fx += gx;
+        fy += gy;
+        fz += gz;
+        atomicAdd(&acc[0][u], -gx);
+        atomicAdd(&acc[1][u], -gy);
+        atomicAdd(&acc[2][u], -gz);
       }
     }
-    io.fx[oi] = fx;
-    io.fy[oi] = fy;
-    io.fz[oi] = fz;
+    unsafeAtomicAdd(&io.fx[oi], fx);
+    unsafeAtomicAdd(&io.fy[oi], fy);
+    unsafeAtomicAdd(&io.fz[oi], fz);
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+    int lo = 0, hi = ntc;  // tile cell of u
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (t.prefix[mid] <= u) lo = mid;
+      else hi = mid;
+    }
+    const int sj = t.src[lo] + (u - t.prefix[lo]);
+    const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
+    const float ax = acc[0][u], ay = acc[1][u], az = acc[2][u];
+    if (ax != 0.0f || ay != 0.0f || az != 0.0f) {
+      unsafeAtomicAdd(&io.fx[oj], ax);
+      unsafeAtomicAdd(&io.fy[oj], ay);
+      unsafeAtomicAdd(&io.fz[oj], az);
+    }
   }
 }
 
@@ -402,9 +437,10 @@ hipError_t desc_adjoint(const float* dEdG, const float* mom, int64_t n, float* c
 
 hipError_t desc_backward(const double* x, const double* y, const double* z,
                          const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
-                         const int32_t* perm, const float* coef, float* fx, float* fy, float* fz,
-                         hipStream_t st) {
+                         const int32_t* perm, const float* coef, int64_t n, float* fx, float* fy,
+                         float* fz, hipStream_t st) {
   DescIO io{nullptr, nullptr, coef, perm, fx, fy, fz};
+  hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
   const unsigned threads = tl.threads < 512 ? tl.threads : 512;
   hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);

@@ -56,15 +56,19 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
   double e = 0.0, w = 0.0;
-  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+  // the plain pass gives each particle two lanes, each taking every other
+  // list word (more waves in flight); the energy pass one lane
+  constexpr int LPP = ENERGY ? 1 : 2;
+  const int part = (int)threadIdx.x % LPP;
+  for (int s = s0 + (int)threadIdx.x / LPP; s < s1; s += (int)blockDim.x / LPP) {
     const double xi = x[s], yi = y[s], zi = z[s];
     const int ngroups = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
     double ax = 0.0, ay = 0.0, az = 0.0, ei = 0.0;
-    uint64_t next = ngroups > 0 ? col[0] : 0;
-    for (int gi = 0; gi < ngroups; ++gi) {
+    uint64_t next = part < ngroups ? col[(int64_t)part * tl.stride] : 0;
+    for (int gi = part; gi < ngroups; gi += LPP) {
       const uint64_t word = next;
-      if (gi + 1 < ngroups) next = col[(int64_t)(gi + 1) * tl.stride];
+      if (gi + LPP < ngroups) next = col[(int64_t)(gi + LPP) * tl.stride];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;  // byte offset in a tile array
@@ -105,6 +109,12 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
         az = __builtin_fma(g, dz, az);
       }
     }
+    if (LPP == 2) {
+      ax += __shfl_xor(ax, 1, 64);
+      ay += __shfl_xor(ay, 1, 64);
+      az += __shfl_xor(az, 1, 64);
+      if (part) continue;
+    }
     const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
     ((OT*)out.fx)[o] = (OT)(ax * scale);
     ((OT*)out.fy)[o] = (OT)(ay * scale);
@@ -141,11 +151,14 @@ template <typename MT, typename OT>
 static void launch_force(bool energy, hipStream_t st, const double* x, const double* y,
                          const double* z, const int32_t* cs, const Grid& g, const TileList& tl,
                          const LJConst& c, const ForceOut& out) {
-  const dim3 grid(tile_grid_blocks(g.nbricks)), block(tl.threads);
+  const dim3 grid(tile_grid_blocks(g.nbricks));
+  const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
   if (energy)
-    hipLaunchKernelGGL((k_lj_force<MT, OT, true>), grid, block, 0, st, x, y, z, cs, g, tl, c, out);
+    hipLaunchKernelGGL((k_lj_force<MT, OT, true>), grid, dim3(tl.threads), 0, st, x, y, z, cs, g, tl,
+                       c, out);
   else
-    hipLaunchKernelGGL((k_lj_force<MT, OT, false>), grid, block, 0, st, x, y, z, cs, g, tl, c, out);
+    hipLaunchKernelGGL((k_lj_force<MT, OT, false>), grid, dim3(two), 0, st, x, y, z, cs, g, tl, c,
+                       out);
 }
 
 hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,
