@@ -7,9 +7,10 @@ rc = 2.5 (energy shifted to zero at rc, so the reported drift measures the
 integration), skin 0.3, dt = 0.001, FP32 pair forces with FP64 positions,
 separations, energies and virial; PE and virial every 10 steps.
 
-A step is one full velocity-Verlet step of the whole path: fused kick+drift,
-(every 10th step) skin check + cell binning + reordering + neighbour-list
-build, force pass (with energy/virial on every 10th), KE reductions.
+A step is one full velocity-Verlet step of the whole path: the force pass
+(with energy/virial on every 10th step) followed in the same kernel by the
+next step's kick-kick-drift, and on every 10th step the skin check, cell
+binning, reordering and neighbour-list build; KE reductions on sampled steps.
 Inputs are resident in HBM before timing starts.
 
 Prints one JSON line (see the keys below).  Progress goes to stderr.
@@ -310,10 +311,12 @@ def main():
     log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
         f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}")
 
-    # algorithmic bytes of one plain force launch: per atom cnt (4) + own
-    # position (24, also the neighbour positions, each read once) + force
-    # (12 as float); per list entry its 16-bit tile offset (2)
-    alg_bytes = n * (4 + 24 + 12) + 2 * entries
+    # algorithmic bytes of one plain force launch, which in the run also applies
+    # the velocity-Verlet kick-kick-drift of the next step: per atom cnt (4) +
+    # own position (24, also the neighbour positions, each read once) +
+    # velocity read and written (48) + new position written (24); per list
+    # entry its 16-bit tile offset (2)
+    alg_bytes = n * (4 + 24 + 48 + 24) + 2 * entries
     avg_s = (f_ms / 1e3) / max(f_n, 1)
     achieved = alg_bytes / avg_s / 1e9
     traffic = measured_traffic()
@@ -342,7 +345,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_lj_force<float,float,false>",
+            "kernel": "k_lj_force<float,float,false> (with the fused kick-kick-drift)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

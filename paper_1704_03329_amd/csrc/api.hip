@@ -51,6 +51,7 @@ struct mdpl_sim {
   void *afx, *afy, *afz;
   int32_t* aids;
   double *xb, *yb, *zb;  // positions at the last build (run)
+  double *px, *py, *pz;  // spare positions: target of the fused drift (run)
   int32_t* offsets;      // n + 1 (export)
   double* partials;      // per-block partials
   int nblk;
@@ -140,10 +141,11 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += 3 * align256(fb * (size_t)n);           // afx..
   b += align256(4 * (size_t)n);                // aids
   b += 3 * align256(8 * (size_t)n);            // xb..
+  b += 3 * align256(8 * (size_t)n);            // px..
   b += align256(2 * (size_t)((p->max_nb + 3) & ~3) * (size_t)npad);  // nbr (16-bit tile indices)
   b += align256(4 * (size_t)npad);             // cnt
   b += align256(4 * (size_t)(n + 1));          // offsets
-  b += align256(8 * (size_t)(2 * nblk + 2));   // partials
+  b += align256(8 * (size_t)(3 * nblk + 2));   // partials
   b += align256(64);                           // flags, maxcount, max_disp, pe_w_tmp
   return b;
 }
@@ -165,9 +167,14 @@ double shift_value(const mdpl_lj_params* p) {
   return 0.0;
 }
 
+// kick (nullable): fuse the velocity-Verlet kick-kick-drift of the next step
+// into the force pass (velocities of *kick updated, new positions to spare,
+// KE of the sampled step to ke_dst); forces are then not stored.
 mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const double* z,
                          void* fx, void* fy, void* fz, const int32_t* scatter, bool energy,
-                         double* e_atom, double* pe_w_dst, int kind, int timing_slot) {
+                         double* e_atom, double* pe_w_dst, int kind, int timing_slot,
+                         const StateArrays* kick = nullptr, double* const* spare = nullptr,
+                         double* ke_dst = nullptr) {
   ForceOut out;
   out.fx = fx;
   out.fy = fy;
@@ -177,6 +184,16 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
   out.partials = s->partials;
   out.scale = 1.0;
   out.scale_dev = nullptr;
+  out.fuse = kick != nullptr;
+  out.vx = kick ? kick->vx : nullptr;
+  out.vy = kick ? kick->vy : nullptr;
+  out.vz = kick ? kick->vz : nullptr;
+  out.nx = kick ? spare[0] : nullptr;
+  out.ny = kick ? spare[1] : nullptr;
+  out.nz = kick ? spare[2] : nullptr;
+  out.h = s->p.dt / (2.0 * s->p.mass);
+  out.dt = s->p.dt;
+  out.flags = s->flags;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (s->timing && timing_slot >= 0) {
     HIP_TRY(hipEventCreate(&e0));
@@ -190,7 +207,10 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
     s->tm.ev[timing_slot].push_back(e0);
     s->tm.ev[timing_slot].push_back(e1);
   }
-  if (energy && pe_w_dst) HIP_TRY(reduce_partials(s->partials, nb, 2, 2, pe_w_dst, 1.0, s->st));
+  const int stride = out.fuse ? 3 : 2;
+  if (energy && pe_w_dst) HIP_TRY(reduce_partials(s->partials, nb, stride, 2, pe_w_dst, 1.0, s->st));
+  if (out.fuse && energy && ke_dst)
+    HIP_TRY(reduce_partials(s->partials + 2, nb, 3, 1, ke_dst, 0.5 * s->p.mass, s->st));
   return MDPL_OK;
 }
 
@@ -257,6 +277,9 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->xb = take<double>(w, 8 * (size_t)n);
   s->yb = take<double>(w, 8 * (size_t)n);
   s->zb = take<double>(w, 8 * (size_t)n);
+  s->px = take<double>(w, 8 * (size_t)n);
+  s->py = take<double>(w, 8 * (size_t)n);
+  s->pz = take<double>(w, 8 * (size_t)n);
   const int max_nb4 = (p->max_nb + 3) & ~3;
   s->tl.nbr = take<uint64_t>(w, 2 * (size_t)max_nb4 * (size_t)s->npad);
   s->tl.cnt = take<int32_t>(w, 4 * (size_t)s->npad);
@@ -265,7 +288,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->tl.threads = threads;
   s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
   s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
-  s->partials = take<double>(w, 8 * (size_t)(2 * s->nblk + 2));
+  s->partials = take<double>(w, 8 * (size_t)(3 * s->nblk + 2));
   char* small = take<char>(w, 64);
   s->flags = (uint32_t*)small;
   s->maxcount = (int32_t*)(small + 4);
@@ -356,6 +379,7 @@ mdpl_status mdpl_lj_backward(mdpl_sim* s, const double* x, const double* y, cons
   out.partials = s->partials;
   out.scale = -1.0;
   out.scale_dev = grad_e;
+  out.fuse = false;
   // FP64 arithmetic for the FP64 context, FP32 pair math for the FP32 one;
   // the gradient is stored in double either way
   const int kind = s->p.precision == MDPL_FP64 ? 2 : 3;
@@ -417,7 +441,7 @@ namespace {
 // fills cur.f* from cur positions (and PE, W into pe_w_dst on sampled steps).
 template <typename ForceFn>
 mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t sample_every,
-                     double* thermo, ForceFn force) {
+                     double* thermo, bool can_fuse, ForceFn force) {
   const int64_t n = s->n;
   const int prec = s->p.precision;
   const int ns = s->p.reuse_every;
@@ -427,6 +451,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
   const double ke_scale = 0.5 * s->p.mass;
   StateArrays alt{s->sx, s->sy, s->sz, s->avx, s->avy, s->avz, s->afx, s->afy, s->afz, s->aids};
   StateArrays cur = user, other = alt;
+  double* spare[3] = {s->px, s->py, s->pz};
   bool have_ref = false;
   s->built = false;  // the standalone build is overwritten
 
@@ -454,7 +479,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
 
   mdpl_status r = rebuild();
   if (r != MDPL_OK) return r;
-  r = force(cur, sampled(0), sampled(0) ? row(0) + 1 : nullptr, -1);
+  r = force(cur, sampled(0), sampled(0) ? row(0) + 1 : nullptr, -1, false, spare, nullptr);
   if (r != MDPL_OK) return r;
   if (sampled(0)) {
     int nb = 0;
@@ -463,19 +488,34 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(0), ke_scale, s->st));
     HIP_TRY(hipMemcpyAsync(row(0) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
   }
+  bool fused = false;  // the last force pass already applied this step's kick-kick-drift
   for (int64_t step = 1; step <= nsteps; ++step) {
-    const bool ke = step > 1 && sampled(step - 1);
-    int nb = 0;
-    HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
-                    h, dt, step == 1 ? 0 : 1, ke, s->partials, s->flags, s->st, &nb));
-    if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(step - 1), ke_scale, s->st));
+    if (!fused) {
+      const bool ke = step > 1 && sampled(step - 1);
+      int nb = 0;
+      HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
+                      h, dt, step == 1 ? 0 : 1, ke, s->partials, s->flags, s->st, &nb));
+      if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(step - 1), ke_scale, s->st));
+    }
     if (step % ns == 0) {
       r = rebuild();
       if (r != MDPL_OK) return r;
     }
     const bool en = sampled(step);
-    r = force(cur, en, en ? row(step) + 1 : nullptr, en ? 1 : 0);
+    // the pass of the last step stores its forces for the final half kick
+    fused = can_fuse && step < nsteps;
+    r = force(cur, en, en ? row(step) + 1 : nullptr, en ? 1 : 0, fused, spare,
+              en ? row(step) : nullptr);
     if (r != MDPL_OK) return r;
+    if (fused) {
+      double* t[3] = {cur.x, cur.y, cur.z};
+      cur.x = spare[0];
+      cur.y = spare[1];
+      cur.z = spare[2];
+      spare[0] = t[0];
+      spare[1] = t[1];
+      spare[2] = t[2];
+    }
     if (en) HIP_TRY(hipMemcpyAsync(row(step) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
   }
   if (nsteps > 0) {
@@ -491,18 +531,23 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     HIP_TRY(disp_partials(cur.x, cur.y, cur.z, s->xb, s->yb, s->zb, n, s->partials, s->st, &nb));
     HIP_TRY(skin_check(s->partials, nb, half_skin, s->max_disp, s->flags, s->st));
   }
-  if (cur.x != user.x) {
+  // the state ends wherever the ping-pong left it: copy back what is not in the caller's arrays
+  {
     const size_t d8 = 8 * (size_t)n, fb = (size_t)s->fbytes * n;
-    HIP_TRY(hipMemcpyAsync(user.x, cur.x, d8, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.y, cur.y, d8, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.z, cur.z, d8, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.vx, cur.vx, d8, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.vy, cur.vy, d8, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.vz, cur.vz, d8, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.fx, cur.fx, fb, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.fy, cur.fy, fb, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.fz, cur.fz, fb, hipMemcpyDeviceToDevice, s->st));
-    HIP_TRY(hipMemcpyAsync(user.ids, cur.ids, 4 * (size_t)n, hipMemcpyDeviceToDevice, s->st));
+    auto back = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+      return dst == src ? hipSuccess
+                        : hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->st);
+    };
+    HIP_TRY(back(user.x, cur.x, d8));
+    HIP_TRY(back(user.y, cur.y, d8));
+    HIP_TRY(back(user.z, cur.z, d8));
+    HIP_TRY(back(user.vx, cur.vx, d8));
+    HIP_TRY(back(user.vy, cur.vy, d8));
+    HIP_TRY(back(user.vz, cur.vz, d8));
+    HIP_TRY(back(user.fx, cur.fx, fb));
+    HIP_TRY(back(user.fy, cur.fy, fb));
+    HIP_TRY(back(user.fz, cur.fz, fb));
+    HIP_TRY(back(user.ids, cur.ids, 4 * (size_t)n));
   }
   return MDPL_OK;
 }
@@ -518,10 +563,12 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
   const int prec = s->p.precision;
   StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
-  return run_loop(s, user, nsteps, sample_every, thermo,
-                  [&](const StateArrays& cur, bool en, double* pe_w, int slot) {
+  return run_loop(s, user, nsteps, sample_every, thermo, true,
+                  [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool fuse,
+                      double* const* spare, double* ke) {
                     return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr,
-                                        en, nullptr, pe_w, prec, slot);
+                                        en, nullptr, pe_w, prec, slot, fuse ? &cur : nullptr,
+                                        spare, ke);
                   });
 }
 
@@ -739,8 +786,9 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
   float* coef = dG + 24 * n;
   const float rc = (float)s->p.rc;
   StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
-  return run_loop(s, user, nsteps, sample_every, thermo,
-                  [&](const StateArrays& cur, bool en, double* pe_w, int slot) -> mdpl_status {
+  return run_loop(s, user, nsteps, sample_every, thermo, false,
+                  [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool,
+                      double* const*, double*) -> mdpl_status {
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (s->timing && slot >= 0) {
                       HIP_TRY(hipEventCreate(&e0));

@@ -144,9 +144,16 @@ struct ForceOut {
   void *fx, *fy, *fz;     // force arrays (float or double)
   const int32_t* scatter; // nullable: slot s writes to scatter[s]
   double* e_atom;         // nullable (scattered like forces)
-  double* partials;       // per-block {pe, w} when energy is on
+  double* partials;       // per-block {pe, w} ({pe, w, 2 ke} when fused) when energy is on
   double scale;           // multiplies the stored force (backward: -grad)
   const double* scale_dev;// nullable: device scalar multiplying the stored force
+  // Fused velocity-Verlet (run loop only; forces are then not stored):
+  // v += h F ; [ke] ; v += h F ; r_new = r + dt v, exactly as vv_step mode 1.
+  bool fuse;
+  double *vx, *vy, *vz;   // velocities, updated in place
+  double *nx, *ny, *nz;   // new positions (a different buffer from x, y, z)
+  double h, dt;
+  uint32_t* flags;        // MDPL_FLAG_NONFINITE on a non-finite velocity
 };
 // Partials are written per brick (nblocks_out = number of bricks).
 hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,

@@ -33,19 +33,45 @@ __device__ __forceinline__ double sq_sum(double dx, double dy, double dz) {
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// The kick-kick-drift of k_vv mode 1 for one particle, same operations in
+// the same order; returns |v|^2 after the first kick (the sampled KE).
+__device__ __forceinline__ double fused_kick(const ForceOut& out, int64_t s, double xi, double yi,
+                                             double zi, double a, double b, double cc, double fx,
+                                             double fy, double fz) {
+#pragma clang fp contract(off)
+  const double gx = out.h * fx, gy = out.h * fy, gz = out.h * fz;
+  a = a + gx;
+  b = b + gy;
+  cc = cc + gz;
+  const double k = (a * a + b * b) + cc * cc;
+  a = a + gx;
+  b = b + gy;
+  cc = cc + gz;
+  out.nx[s] = xi + out.dt * a;
+  out.ny[s] = yi + out.dt * b;
+  out.nz[s] = zi + out.dt * cc;
+  out.vx[s] = a;
+  out.vy[s] = b;
+  out.vz[s] = cc;
+  const double m2 = (a * a + b * b) + cc * cc;
+  if (!(m2 < 1e300)) atomicOr(out.flags, MDPL_FLAG_NONFINITE);
+  return k;
+}
+
 // One workgroup per brick: the tile holds the image positions of the brick's
 // neighbourhood, so a pair needs one LDS gather and plain FP64 differences.
 // MT: arithmetic type of the pair force; OT: stored force type.  The pair
 // force is accumulated in FP64 (one conversion of the scalar factor per pair
 // instead of three of the separation).
+// The plain pass asks for 8 waves per SIMD (<= 64 VGPRs), so that two
+// 1024-thread workgroups (LDS: two tiles) share a CU.
 template <typename MT, typename OT, bool ENERGY>
-__global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
-                                                   const double* __restrict__ y,
-                                                   const double* __restrict__ z,
-                                                   const int32_t* __restrict__ cs, Grid g,
-                                                   TileList tl, LJConst c, ForceOut out) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ENERGY ? 1 : 8)))
+void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
+                const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g, TileList tl,
+                LJConst c, ForceOut out) {
   __shared__ TileShared t;
-  __shared__ double red[32];  // up to 16 waves: e, then w
+  __shared__ double red[48];  // up to 16 waves: e, w, ke
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
@@ -55,13 +81,20 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
   const MT c48 = (MT)(48.0 * c.eps), c24 = (MT)(24.0 * c.eps);
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
-  double e = 0.0, w = 0.0;
+  double e = 0.0, w = 0.0, ke = 0.0;
   // the plain pass gives each particle two lanes, each taking every other
   // list word (more waves in flight); the energy pass one lane
   constexpr int LPP = ENERGY ? 1 : 2;
   const int part = (int)threadIdx.x % LPP;
   for (int s = s0 + (int)threadIdx.x / LPP; s < s1; s += (int)blockDim.x / LPP) {
     const double xi = x[s], yi = y[s], zi = z[s];
+    // velocities for the fused kick, loaded early so the pair loop hides the latency
+    double vxi = 0.0, vyi = 0.0, vzi = 0.0;
+    if (out.fuse && part == 0) {
+      vxi = out.vx[s];
+      vyi = out.vy[s];
+      vzi = out.vz[s];
+    }
     const int ngroups = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
     double ax = 0.0, ay = 0.0, az = 0.0, ei = 0.0;
@@ -115,6 +148,13 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
       az += __shfl_xor(az, 1, 64);
       if (part) continue;
     }
+    if (out.fuse) {
+      // the kicks use the force as stored (rounded to OT), like k_vv
+      ke += fused_kick(out, s, xi, yi, zi, vxi, vyi, vzi, (double)(OT)(ax * scale),
+                       (double)(OT)(ay * scale), (double)(OT)(az * scale));
+      if (ENERGY) e += ei;
+      continue;
+    }
     const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
     ((OT*)out.fx)[o] = (OT)(ax * scale);
     ((OT*)out.fy)[o] = (OT)(ay * scale);
@@ -128,21 +168,30 @@ __global__ __launch_bounds__(1024) void k_lj_force(const double* __restrict__ x,
     // brick sums: wave butterflies, then the wave sums in order
     e = wave_sum(e);
     w = wave_sum(w);
+    ke = wave_sum(ke);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
       red[wave] = e;
       red[16 + wave] = w;
+      red[32 + wave] = ke;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int nw = (blockDim.x + 63) >> 6;
-      double pe = 0.0, ww = 0.0;
+      double pe = 0.0, ww = 0.0, kk = 0.0;
       for (int k = 0; k < nw; ++k) {
         pe += red[k];
         ww += red[16 + k];
+        kk += red[32 + k];
       }
-      out.partials[2 * brick] = pe;
-      out.partials[2 * brick + 1] = ww;
+      if (out.fuse) {
+        out.partials[3 * brick] = pe;
+        out.partials[3 * brick + 1] = ww;
+        out.partials[3 * brick + 2] = kk;
+      } else {
+        out.partials[2 * brick] = pe;
+        out.partials[2 * brick + 1] = ww;
+      }
     }
   }
 }
