@@ -113,7 +113,10 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
           // pair energy and virial in FP64 on the sampled steps
           const double d2 = sq_sum(dx, dy, dz);
           const bool in = d2 < c.rc2;
-          const double inv = 1.0 / d2;
+          // reciprocal: hardware estimate and two Newton steps (a few ulp)
+          double inv = __builtin_amdgcn_rcp(d2);
+          inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
+          inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
           const double s2 = c.sigma2 * inv;
           const double s6 = s2 * s2 * s2;
           const double gg = 48.0 * c.eps * inv * s6 * (s6 - 0.5);

@@ -103,7 +103,9 @@ __device__ __forceinline__ void scan_range(const TileShared& t, int ub, int ue, 
   }
 }
 
-__global__ __launch_bounds__(1024) void k_build_tile_nlist(
+// One wave per home cell (up to 16 per workgroup); at most 64 VGPRs so that two
+// 1024-thread workgroups (LDS: two tiles) share a CU.
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_build_tile_nlist(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
     TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
@@ -220,7 +222,8 @@ hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
                             const int32_t* skeys, const int32_t* cell_start, const Grid& g,
                             double r2, TileList tl, uint32_t* flags, int32_t* maxcount,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_build_tile_nlist, dim3(tile_grid_blocks(g.nbricks)), dim3(tl.threads), 0, st,
+  const unsigned threads = g.V * 64 < 1024 ? (unsigned)g.V * 64 : 1024u;
+  hipLaunchKernelGGL(k_build_tile_nlist, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st,
                      x, y, z, skeys, cell_start, g, r2, tl, flags, maxcount);
   return hipGetLastError();
 }
