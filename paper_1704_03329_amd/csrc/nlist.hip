@@ -16,6 +16,8 @@
 //  * the analysis list (bond order / CNA): one thread per particle walks the
 //    9 rows of 3 consecutive cells in global memory, entries are sorted-slot
 //    indices, row-major so a whole list is one contiguous read.
+#include <math.h>
+
 #include "device_util.h"
 #include "internal.h"
 #include "tile.h"
@@ -32,26 +34,28 @@ namespace mdpl {
 // per-particle LDS counter and are stored as 16-bit halves of the list
 // words; a final pass pads the last word and writes the counts.
 //
-// Rows without a periodic image (code 21 in all three cells) use the stored
-// positions directly, which is exactly the definition's arithmetic; image
-// cells apply their known shift (scan_range).
-// Separation of a tile candidate under the three ways of forming the
-// definition's minimum image:
-//   PLAIN: the cell is no periodic image (the wrap never applies);
-//   SHIFT: the cell is the image shifted by (sx, sy, sz) boxes and the grid
-//          has >= 5 cells per axis, so the wrap applies exactly on the
-//          shifted axes (|xi - xj| > L/2 there, < L/2 elsewhere):
-//          dx = fl(fl(xi - xj) - sx L), with sx L = 0 an exact no-op;
-//   EXACT: the conditional wrap itself (small grids).
-enum { kPlain = 0, kShift = 1, kExact = 2 };
+// Exactness with an FP32 screen.  The tile holds FP32 positions relative to
+// its corner with the periodic image already applied, X = fl32((x + s L) - o).
+// Each coordinate is then within 2^-24 span of the exact image (span = tile
+// extent), a difference within 2^-24 (2 span + 2 r_ext) of the exact one,
+// and the FP32 squared distance d2f of any pair near the list radius
+// within e = 2 sqrt(3) r_ext 2^-24 (2 span + 2 r_ext) + 3 2^-24 r^2 of the
+// definition's d2 (whose own rounding is ~1e-14).  With the guard band
+// g = 8 e, d2f < r^2 - g proves d2 < r^2 and d2f > r^2 + g proves d2 >= r^2;
+// the rare pairs in between are decided by the definition itself (the
+// conditional minimum image on the stored FP64 positions).  The list is
+// therefore bit-identical to the all-pairs definition.
+constexpr float kFarF = 1e30f;  // dummy slot: its d2f overflows to +inf
 
 struct RowScan {
-  double xi, yi, zi, r2;
-  double sLx, sLy, sLz;      // SHIFT offsets
-  double Lx, Ly, Lz, hx, hy, hz;
-  int self, K, max_nb;
-  int* cnt;                  // the particle's LDS counter
-  uint16_t* base;            // its list: entry m at base[(m >> 2) * stride4 + (m & 3)]
+  float xi, yi, zi;            // FP32 tile coordinates of the particle
+  float r2lo, r2hi;            // r^2 -/+ g
+  double xs, ys, zs;           // its stored FP64 position (exact test)
+  const double *x, *y, *z;     // stored FP64 positions, sorted slots
+  double r2, Lx, Ly, Lz, hx, hy, hz;
+  int self, K, max_nb, ntc;
+  int* cnt;                    // the particle's LDS counter
+  uint16_t* base;              // its list: entry m at base[(m >> 2) * stride4 + (m & 3)]
   uint32_t stride4;
 };
 
@@ -59,9 +63,9 @@ struct RowScan {
 // indices), UNROLL at a time so that their LDS loads overlap; slots past the
 // end read the far-away dummy.  One LDS atomic reserves the ranks of all
 // accepted candidates of a step.
-template <int MODE, int UNROLL>
-__device__ __forceinline__ void scan_range(const TileShared& t, int ub, int ue, const RowScan& q) {
-#pragma clang fp contract(off)
+template <int UNROLL>
+__device__ __forceinline__ void scan_range(const TileShared32& t, int ub, int ue,
+                                           const RowScan& q) {
   for (int u0 = ub; u0 < ue; u0 += UNROLL * q.K) {
     int uu[UNROLL];
     bool acc[UNROLL];
@@ -73,20 +77,17 @@ __device__ __forceinline__ void scan_range(const TileShared& t, int ub, int ue, 
     }
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
-      const double xj = t.x[uu[j]], yj = t.y[uu[j]], zj = t.z[uu[j]];
-      double d2;
-      if (MODE == kExact) {
-        d2 = exact_d2(q.xi, q.yi, q.zi, xj, yj, zj, q.Lx, q.Ly, q.Lz, q.hx, q.hy, q.hz);
-      } else {
-        double dx = q.xi - xj, dy = q.yi - yj, dz = q.zi - zj;
-        if (MODE == kShift) {
-          dx = dx - q.sLx;
-          dy = dy - q.sLy;
-          dz = dz - q.sLz;
-        }
-        d2 = (dx * dx + dy * dy) + dz * dz;
+      const float dx = q.xi - t.x[uu[j]], dy = q.yi - t.y[uu[j]], dz = q.zi - t.z[uu[j]];
+      const float d2f = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+      const bool other = uu[j] != q.self;
+      acc[j] = other && d2f < q.r2lo;
+      if (other && !(d2f < q.r2lo) && d2f <= q.r2hi) {
+        // inside the guard band: the definition decides
+        const int c = tile_cell_of(t, q.ntc, uu[j]);
+        const int sj = t.src[c] + (uu[j] - t.prefix[c]);
+        acc[j] = exact_d2(q.xs, q.ys, q.zs, q.x[sj], q.y[sj], q.z[sj], q.Lx, q.Ly, q.Lz, q.hx, q.hy,
+                          q.hz) < q.r2;
       }
-      acc[j] = d2 < q.r2 && uu[j] != q.self;
       na += acc[j] ? 1 : 0;
     }
     if (na) {
@@ -103,13 +104,13 @@ __device__ __forceinline__ void scan_range(const TileShared& t, int ub, int ue, 
   }
 }
 
-// One wave per home cell (up to 16 per workgroup); at most 64 VGPRs so that two
-// 1024-thread workgroups (LDS: two tiles) share a CU.
+// One wave per home cell (up to 16 per workgroup); at most 64 VGPRs so that
+// two 1024-thread workgroups share a CU.
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_build_tile_nlist(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
-    TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
-  __shared__ TileShared t;
+    float guard, TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
+  __shared__ TileShared32 t;
   __shared__ int acnt[kBrickMax];
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
@@ -119,17 +120,37 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   if (threadIdx.x == 0 && (total > kTileCap || nbrick > kBrickMax))
     atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
   for (int a = threadIdx.x; a < kBrickMax; a += blockDim.x) acnt[a] = 0;
-  tile_load<false>(g, x, y, z, total, t);  // ends with a barrier
   const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
-  const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
-  const bool shift_ok = g.nc[0] >= 5 && g.nc[1] >= 5 && g.nc[2] >= 5;
   const int TX = g.B[0] + 2, TXY = TX * (g.B[1] + 2);
+  const int ntc = TXY * (g.B[2] + 2);
+  int bx, by, bz;
+  brick_coords(g, brick, bx, by, bz);
+  // the tile corner (one cell below the brick) and FP32 relative image positions
+  const double ox = (double)(bx * g.B[0] - 1) * (Lx / g.nc[0]);
+  const double oy = (double)(by * g.B[1] - 1) * (Ly / g.nc[1]);
+  const double oz = (double)(bz * g.B[2] - 1) * (Lz / g.nc[2]);
+  {
+    const int nt = total < kTileCap ? total : kTileCap;
+    if (threadIdx.x == 0) {
+      t.x[kTileDummy] = kFarF;
+      t.y[kTileDummy] = kFarF;
+      t.z[kTileDummy] = kFarF;
+    }
+    for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+      const int c = tile_cell_of(t, ntc, u);
+      const int src = t.src[c] + (u - t.prefix[c]);
+      const int code = t.code[c];
+      t.x[u] = (float)((x[src] + (double)((code & 3) - 1) * Lx) - ox);
+      t.y[u] = (float)((y[src] + (double)(((code >> 2) & 3) - 1) * Ly) - oy);
+      t.z[u] = (float)((z[src] + (double)(((code >> 4) & 3) - 1) * Lz) - oz);
+    }
+    __syncthreads();
+  }
   const int max_nb = tl.max_nb;
   uint16_t* __restrict__ half = (uint16_t*)tl.nbr;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  int bx, by, bz;
-  brick_coords(g, brick, bx, by, bz);
+  const float r2lo = (float)(r2 - (double)guard), r2hi = (float)(r2 + (double)guard);
   for (int lc = wave; lc < g.V; lc += nwaves) {
     const int lx = lc % g.B[0], ly = (lc / g.B[0]) % g.B[1], lz = lc / (g.B[0] * g.B[1]);
     // the last brick along an axis may be partial: its missing cells would
@@ -149,50 +170,39 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       const int la = s - s0;            // its index within the brick
       const bool ok = active && self < kTileCap && la >= 0 && la < kBrickMax && s < s1;
       RowScan q;
-      q.xi = ok ? t.x[self] : 0.0;
-      q.yi = ok ? t.y[self] : 0.0;
-      q.zi = ok ? t.z[self] : 0.0;
+      q.xi = ok ? t.x[self] : 0.0f;
+      q.yi = ok ? t.y[self] : 0.0f;
+      q.zi = ok ? t.z[self] : 0.0f;
+      q.r2lo = r2lo;
+      q.r2hi = r2hi;
+      q.xs = ok ? x[s] : 0.0;
+      q.ys = ok ? y[s] : 0.0;
+      q.zs = ok ? z[s] : 0.0;
+      q.x = x;
+      q.y = y;
+      q.z = z;
       q.r2 = r2;
       q.Lx = Lx;
       q.Ly = Ly;
       q.Lz = Lz;
-      q.hx = hx;
-      q.hy = hy;
-      q.hz = hz;
+      q.hx = 0.5 * Lx;
+      q.hy = 0.5 * Ly;
+      q.hz = 0.5 * Lz;
       q.self = self;
       q.K = K;
       q.max_nb = max_nb;
+      q.ntc = ntc;
       q.cnt = &acnt[ok ? la : 0];
       q.base = half + (int64_t)(ok ? s : 0) * 4;
       q.stride4 = (uint32_t)(tl.stride * 4);
       for (int oz = -1; oz <= 1; ++oz) {
-        for (int oy = -1; oy <= 1; ++oy) {
+        for (int oy2 = -1; oy2 <= 1; ++oy2) {
           // a stencil row: three consecutive tile cells, one contiguous index range
-          const int tcl = tc0 + oz * TXY + oy * TX - 1;
-          const int c0 = t.code[tcl], c1 = t.code[tcl + 1], c2 = t.code[tcl + 2];
+          const int tcl = tc0 + oz * TXY + oy2 * TX - 1;
           if (!ok) continue;
-          if (c0 == 21 && c1 == 21 && c2 == 21) {
-            int ue = t.prefix[tcl + 3];
-            ue = ue < kTileCap ? ue : kTileCap;
-            scan_range<kPlain, 4>(t, t.prefix[tcl] + k, ue, q);
-            continue;
-          }
-          for (int tc = tcl; tc < tcl + 3; ++tc) {
-            const int code = t.code[tc];
-            int ue = t.prefix[tc + 1];
-            ue = ue < kTileCap ? ue : kTileCap;
-            const int ub = t.prefix[tc] + k;
-            if (code == 21) {
-              scan_range<kPlain, 4>(t, ub, ue, q);
-            } else if (shift_ok) {
-              q.sLx = (double)((code & 3) - 1) * Lx;
-              q.sLy = (double)(((code >> 2) & 3) - 1) * Ly;
-              q.sLz = (double)(((code >> 4) & 3) - 1) * Lz;
-              scan_range<kShift, 4>(t, ub, ue, q);
-            } else {
-              scan_range<kExact, 4>(t, ub, ue, q);
-            }
-          }
+          int ue = t.prefix[tcl + 3];
+          ue = ue < kTileCap ? ue : kTileCap;
+          scan_range<4>(t, t.prefix[tcl] + k, ue, q);
         }
       }
     }
@@ -223,8 +233,18 @@ hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
                             double r2, TileList tl, uint32_t* flags, int32_t* maxcount,
                             hipStream_t st) {
   const unsigned threads = g.V * 64 < 1024 ? (unsigned)g.V * 64 : 1024u;
+  // guard band of the FP32 screen (see the derivation above k_build_tile_nlist)
+  double span = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double e = (double)(g.B[k] + 2) * (g.box[k] / g.nc[k]);
+    span = e > span ? e : span;
+  }
+  const double u32 = 1.0 / 16777216.0;  // 2^-24
+  const double rext = sqrt(r2);
+  const double err = 2.0 * sqrt(3.0) * rext * u32 * (2.0 * span + 2.0 * rext) + 3.0 * u32 * r2;
+  const float guard = (float)(8.0 * err);
   hipLaunchKernelGGL(k_build_tile_nlist, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st,
-                     x, y, z, skeys, cell_start, g, r2, tl, flags, maxcount);
+                     x, y, z, skeys, cell_start, g, r2, guard, tl, flags, maxcount);
   return hipGetLastError();
 }
 

@@ -18,14 +18,17 @@
 
 namespace mdpl {
 
-struct TileShared {
-  double x[kTileMax];
-  double y[kTileMax];
-  double z[kTileMax];
+template <typename T>
+struct TileOf {
+  T x[kTileMax];
+  T y[kTileMax];
+  T z[kTileMax];
   int prefix[kTileCells + 1];
   int src[kTileCells];
   int code[kTileCells];
 };
+using TileShared = TileOf<double>;  // FP64 image positions (force and descriptor passes)
+using TileShared32 = TileOf<float>; // FP32 positions relative to the tile origin (list build)
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // run of bricks (a slab of the box) so that tile reloads hit its own L2.
@@ -44,8 +47,8 @@ __device__ __forceinline__ void brick_coords(const Grid& g, int brick, int& bx, 
 
 // Fills prefix/src/code for the tile of `brick`; returns the particle count
 // (possibly above kTileMax).  Ends with a barrier.
-__device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __restrict__ cs,
-                                 TileShared& t) {
+template <typename TS>
+__device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __restrict__ cs, TS& t) {
   const int TX = g.B[0] + 2, TY = g.B[1] + 2, TZ = g.B[2] + 2;
   const int ntc = TX * TY * TZ;
   int bx, by, bz;
@@ -118,6 +121,18 @@ __device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
     t.z[u] = c;
   }
   __syncthreads();
+}
+
+// Tile cell of tile particle u < total (binary search over the prefix).
+template <typename TS>
+__device__ __forceinline__ int tile_cell_of(const TS& t, int ntc, int u) {
+  int lo = 0, hi = ntc;  // prefix[lo] <= u < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (t.prefix[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
 // slot[u] = sorted slot of tile particle u (u < min(total, kTileCap)).
