@@ -253,7 +253,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "domain decomposition is not part of this build", file=sys.stderr)
+              "domain decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

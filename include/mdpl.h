@@ -205,7 +205,7 @@ mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t 
 
 
 /* ------------------------------------------------------- learned potential
- * (North-star extension, not in the paper.)  Descriptors of the particles of
+ * (An extension; not in the paper.)  Descriptors of the particles of
  * the last mdpl_build with cutoff rc: 16 radial Gaussians
  * exp(-eta_r (r - R_k)^2) fc(r), R_k = 0.85 + 0.11 k, eta_r = 1/(2*0.11^2),
  * and 8 angular sums 2^(1-zeta) sum_{j != k} (1 + lam cos t_jik)^zeta w_j w_k,
