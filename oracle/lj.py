@@ -175,8 +175,11 @@ def wrap(pos, box):
 
 
 def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float = 1.0, sigma: float = 1.0,
-                    mass: float = 1.0, shift: str = "none", sample_every: int = 0):
+                    mass: float = 1.0, shift: str = "none", sample_every: int = 0, force_fn=None):
     """Velocity Verlet exactly in the order of Alg. VelocityVerlet.
+
+    force_fn(x) -> dict(F, pe, w) replaces the LJ force field when given
+    (the algorithm is the same for any force field).
 
     F(r_0) is computed before the first step (the algorithm uses F in its
     first half kick without showing its computation).  Per step:
@@ -191,7 +194,10 @@ def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float
     x = np.array(pos, dtype=np.float64, copy=True)
     v = np.array(vel, dtype=np.float64, copy=True)
     h = dt / (2.0 * mass)
-    res = lj_forces(x, box, rc, eps, sigma, shift)
+    if force_fn is None:
+        def force_fn(r):
+            return lj_forces(r, box, rc, eps, sigma, shift)
+    res = force_fn(x)
     F = res["F"]
     thermo = []
     if sample_every:
@@ -199,7 +205,7 @@ def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float
     for step in range(1, nsteps + 1):
         v = v + h * F
         x = x + dt * v
-        res = lj_forces(x, box, rc, eps, sigma, shift)
+        res = force_fn(x)
         F = res["F"]
         v = v + h * F
         if sample_every and step % sample_every == 0:
