@@ -180,3 +180,50 @@ def test_training_beats_linear_and_untrained(small_training_set):
     print(f"validation MAE: untrained {mae0:.4f}, linear {mae_lin:.4f}, trained {mae1:.4f}; losses {losses}")
     assert losses[-1][1] < losses[0][1]
     assert mae1 < mae_lin and mae1 < mae0
+
+
+def test_run_mlp_matches_oracle_velocity_verlet():
+    """mdpl_run_mlp (list reuse, reordering, the network as force field)
+    against the oracle's velocity Verlet (Alg. VelocityVerlet) with oracle
+    network forces and the same bf16-rounded weights: 864 atoms, 5 steps.
+    The device's activations are bf16 on the matrix cores (forces within
+    2e-2), so positions agree to dt^2 x that over the run."""
+    from oracle import lj as olj
+    from paper_1704_03329_amd import potential as P
+    from paper_1704_03329_amd.sim import LJSim
+
+    gpu_device()
+    d = mdinputs.fcc_lj(6, temperature=1.0, seed=8)
+    pos = mdinputs.perturb(d["pos"], 0.05, 9)
+    box = d["box"]
+    n = pos.shape[0]
+    sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=2, precision="fp32")
+    G0 = P.descriptors(LJSim(n, box, rc=2.5, skin=0.3, precision="fp64"), torch.from_numpy(pos).cuda())
+    m = _model(G0, torch.from_numpy(np.linspace(-6, -3, n)).cuda(), seed=5)
+    st = sim.new_state(torch.from_numpy(pos), torch.from_numpy(d["vel"]))
+    ws = torch.empty(P.mdpl_mlp_run_floats(n), dtype=torch.float32, device="cuda")
+    th = torch.empty((6, 4), dtype=torch.float64, device="cuda")
+    P.mdpl_run_mlp(sim, m.weights(), ws, st, 5, 1, th)
+    assert sim.check(raise_on_error=False)[0] == 0
+    p = m.host_params()
+    mu, sd = m.mu.double().cpu().numpy(), m.sd.double().cpu().numpy()
+
+    def force_fn(x):
+        G, table, grads = OD.descriptors(x, box, with_grad=True)
+        E, dEdG = OM.energy_and_feature_grad(p, G, mu, sd, m.e_mean, m.e_sd)
+        return {"F": OD.forces_from_feature_grad(n, np.arange(n), table, grads, dEdG), "pe": float(E.sum()),
+                "w": 0.0}
+
+    ref = olj.velocity_verlet(pos, d["vel"], box, 5, 0.001, 2.5, sample_every=1, force_fn=force_fn)
+    ids = st["ids"].cpu().numpy()
+    got_x = np.zeros((n, 3))
+    got_v = np.zeros((n, 3))
+    got_x[ids] = torch.stack([st["x"], st["y"], st["z"]], 1).cpu().numpy()
+    got_v[ids] = torch.stack([st["vx"], st["vy"], st["vz"]], 1).cpu().numpy()
+    dx = got_x - ref["pos"]
+    dx -= box * np.round(dx / box)  # the device folds positions into the box at rebuilds
+    assert np.max(np.abs(dx)) <= 1e-6
+    assert np.linalg.norm(got_v - ref["vel"]) <= 2e-3 * np.linalg.norm(ref["vel"])
+    t = th.cpu().numpy()
+    np.testing.assert_allclose(t[:, 0], ref["thermo"][:, 1], rtol=1e-4)  # KE
+    np.testing.assert_allclose(t[:, 1], ref["thermo"][:, 2], rtol=2e-2)  # sum of network energies
