@@ -329,7 +329,9 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
 // - dE_j/du_ja), so each thread needs only its own K_i: it adds g_ij to its
 // particle and subtracts it from the neighbour's LDS accumulator; the block
 // then adds its accumulators to the outputs with global atomics (the output
-// is zeroed first).  FP32 atomics make the last bits of the forces depend on
+// is zeroed first).  Two lanes share a particle, each taking every other
+// list word (twice the waves in flight; the 128-VGPR bound of 1024-thread
+// workgroups spills a few registers, which costs less than it gains).  FP32 atomics make the last bits of the forces depend on
 // the order in which blocks and waves land.
 __global__ void k_zero3(float* __restrict__ a, float* __restrict__ b, float* __restrict__ c,
                         int64_t n) {
@@ -341,7 +343,7 @@ __global__ void k_zero3(float* __restrict__ a, float* __restrict__ b, float* __r
   }
 }
 
-__global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
+__global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    const double* __restrict__ z,
                                                    const int32_t* __restrict__ cs, Grid g,
@@ -363,7 +365,8 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
   const double rc2 = (double)rc * (double)rc;
   const float pi_rc = 3.14159265358979f / rc;
   const float half_rev = 0.5f / rc;
-  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+  const int part = (int)threadIdx.x & 1;  // two lanes per particle, alternate list words
+  for (int s = s0 + ((int)threadIdx.x >> 1); s < s1; s += (int)(blockDim.x >> 1)) {
     const double xi = x[s], yi = y[s], zi = z[s];
     const int64_t oi = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
     float Ki[68];
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     const int ng = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
-    for (int gi = 0; gi < ng; ++gi) {
+    for (int gi = part; gi < ng; gi += 2) {
       const uint64_t word = col[(int64_t)gi * tl.stride];
       for (int q = 0; q < 4; ++q) {
         const int u = (int)((word >> (16 * q)) & 0xffff) >> 3;
@@ -441,7 +444,7 @@ hipError_t desc_backward(const double* x, const double* y, const double* z,
                          float* fz, hipStream_t st) {
   DescIO io{nullptr, nullptr, coef, perm, fx, fy, fz};
   hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
-  const unsigned threads = tl.threads < 512 ? tl.threads : 512;
+  const unsigned threads = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
   hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);
   return hipGetLastError();
