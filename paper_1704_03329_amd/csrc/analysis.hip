@@ -33,6 +33,7 @@ __device__ __forceinline__ float qweight(int l, int m) {
   return (float)r;
 }
 
+template <bool Q5>
 __global__ __launch_bounds__(256) void k_boa(const double* __restrict__ sx,
                                              const double* __restrict__ sy,
                                              const double* __restrict__ sz,
@@ -74,8 +75,8 @@ __global__ __launch_bounds__(256) void k_boa(const double* __restrict__ sx,
               exact_sep(xi, yi, zi, sx[t], sy[t], sz[t], Lx, Ly, Lz, hx, hy, hz, dx, dy, dz);
           if (!(d2 < rc2)) continue;
           ++nu;
-          const double ir = 1.0 / sqrt(d2);
-          const float ux = (float)(dx * ir), uy = (float)(dy * ir), uz = (float)(dz * ir);
+          const float ir = __builtin_amdgcn_rsqf((float)d2);  // the bond test above is FP64
+          const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
           // (x + i y)^m, m = 0..6
           float cr[7], ci[7];
           cr[0] = 1.0f;
@@ -100,7 +101,8 @@ __global__ __launch_bounds__(256) void k_boa(const double* __restrict__ sx,
               else if (l == m + 1)
                 p = (float)(2 * m + 1) * uz * dfact;
               else
-                p = ((float)(2 * l - 1) * uz * pm1 - (float)(l + m - 1) * pm2) / (float)(l - m);
+                p = ((float)(2 * l - 1) * uz * pm1 - (float)(l + m - 1) * pm2) *
+                    (1.0f / (float)(l - m));
               if (l > m) {
                 pm2 = pm1;
                 pm1 = p;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(256) void k_boa(const double* __restrict__ sx,
               if (l == 4) {
                 A4[m] += p * cr[m];
                 B4[m] += p * ci[m];
-              } else if (l == 5) {
+              } else if (Q5 && l == 5) {
                 A5[m] += p * cr[m];
                 B5[m] += p * ci[m];
               } else if (l == 6) {
@@ -139,8 +141,12 @@ __global__ __launch_bounds__(256) void k_boa(const double* __restrict__ sx,
 hipError_t boa_q(const double* sx, const double* sy, const double* sz, const int32_t* skeys,
                  const int32_t* cell_start, const int32_t* perm, int64_t n, const Grid& g,
                  double rc2, float* q4, float* q5, float* q6, int32_t* nnb, hipStream_t st) {
-  hipLaunchKernelGGL(k_boa, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, sx, sy, sz, skeys,
-                     cell_start, perm, n, g, rc2, q4, q5, q6, nnb);
+  if (q5)
+    hipLaunchKernelGGL(k_boa<true>, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, sx, sy, sz,
+                       skeys, cell_start, perm, n, g, rc2, q4, q5, q6, nnb);
+  else
+    hipLaunchKernelGGL(k_boa<false>, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, sx, sy, sz,
+                       skeys, cell_start, perm, n, g, rc2, q4, q5, q6, nnb);
   return hipGetLastError();
 }
 
@@ -171,7 +177,17 @@ __global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const int32_t* __
     return;
   }
   const int32_t* row = nl.nbr + s * (int64_t)max_nb;
-  for (int k = 0; k < ni; ++k) L[k][tid] = row[k];
+  // N(i) in ascending slot order (insertion sort), so that membership is a
+  // binary search; the triplets count bonds and do not depend on the order
+  for (int k = 0; k < ni; ++k) {
+    const int32_t v = row[k];
+    int b = k - 1;
+    while (b >= 0 && L[b][tid] > v) {
+      L[b + 1][tid] = L[b][tid];
+      --b;
+    }
+    L[b + 1][tid] = v;
+  }
   // adjacency among the neighbours of i (bonds of Ebar(i) with both ends in N(i))
   for (int a = 0; a < ni; ++a) {
     const int32_t v = L[a][tid];
@@ -181,7 +197,13 @@ __global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const int32_t* __
     uint32_t mask = 0;
     for (int q = 0; q < nv; ++q) {
       const int32_t w = rv[q];
-      for (int b = 0; b < ni; ++b) mask |= (L[b][tid] == w) ? (1u << b) : 0u;
+      int lo = 0, hi = ni;  // first index with L >= w
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (L[mid][tid] < w) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < ni && L[lo][tid] == w) mask |= 1u << lo;
     }
     adj[a][tid] = mask;
   }
