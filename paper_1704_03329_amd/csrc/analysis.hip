@@ -158,13 +158,15 @@ __device__ __forceinline__ uint32_t pack_triplet(int ncn, int nb, int nlcb) {
   return ((uint32_t)ncn << 20) | ((uint32_t)nb << 10) | (uint32_t)nlcb;
 }
 
+// MAXNB: LDS columns per thread (16 or 32); fewer columns, more waves per CU.
+template <int MAXNB>
 __global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const int32_t* __restrict__ perm,
                                                      int64_t n, uint32_t* __restrict__ trip,
                                                      int32_t* __restrict__ nnb,
                                                      uint8_t* __restrict__ label, int max_out) {
   // per-thread columns: L[k][tid] neighbour k of i; adj[k][tid] its mask
-  __shared__ int32_t L[kCnaMax][kCnaThreads];
-  __shared__ uint32_t adj[kCnaMax][kCnaThreads];
+  __shared__ int32_t L[MAXNB][kCnaThreads];
+  __shared__ uint32_t adj[MAXNB][kCnaThreads];
   const int tid = threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * kCnaThreads + tid;
   if (s >= n) return;
@@ -265,8 +267,12 @@ __global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const int32_t* __
 
 hipError_t cna_signatures(const NList& nl, const int32_t* perm, int64_t n, uint32_t* trip,
                           int32_t* nnb, uint8_t* label, int max_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_cna, dim3((unsigned)div_up(n, kCnaThreads)), dim3(kCnaThreads), 0, st, nl,
-                     perm, n, trip, nnb, label, max_out);
+  if (nl.max_nb <= 16)
+    hipLaunchKernelGGL(k_cna<16>, dim3((unsigned)div_up(n, kCnaThreads)), dim3(kCnaThreads), 0, st,
+                       nl, perm, n, trip, nnb, label, max_out);
+  else
+    hipLaunchKernelGGL(k_cna<kCnaMax>, dim3((unsigned)div_up(n, kCnaThreads)), dim3(kCnaThreads), 0,
+                       st, nl, perm, n, trip, nnb, label, max_out);
   return hipGetLastError();
 }
 
