@@ -217,14 +217,12 @@ mdpl_status mdpl_desc_fwd(mdpl_sim* sim, const double* x, const double* y, const
                           float* G, float* mom);
 
 /* Forces F_i = -dE/dr_i of E = sum_i E_i(G_i), from dEdG (n x 24, dE_i/dG_i)
- * and mom of mdpl_desc_fwd at the same positions.  coef: n x 68 float
- * scratch (caller-owned).  fx, fy, fz: float, caller order, overwritten.
- * The pair terms are summed with FP32 atomics, so the last bits of the
- * forces may differ between runs (the sum of all forces stays zero to
- * rounding). */
+ * and mom of mdpl_desc_fwd at the same positions.  fx, fy, fz: float,
+ * caller order, overwritten.  The pair terms are summed with FP32 atomics,
+ * so the last bits of the forces may differ between runs (the sum of all
+ * forces stays zero to rounding). */
 mdpl_status mdpl_desc_bwd(mdpl_sim* sim, const double* x, const double* y, const double* z,
-                          const float* dEdG, const float* mom, float* coef, float* fx, float* fy,
-                          float* fz);
+                          const float* dEdG, const float* mom, float* fx, float* fy, float* fz);
 
 /* Network 24 -> 64 -> 64 -> 1 with SiLU: inputs g = (G - mu) / sd padded
  * to 32, E = e_mean + e_sd (w3 . silu(W2 silu(W1 g + b1) + b2) + b3).
@@ -274,8 +272,8 @@ mdpl_status mdpl_adam_step(float* params, const float* grad, float* m, float* v,
 mdpl_status mdpl_scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
                                   void* stream);
 
-/* Floats of caller workspace mdpl_run_mlp needs for n particles (167 n:
- * features, moments, energies, dE/dG, adjoint coefficients). */
+/* Floats of caller workspace mdpl_run_mlp needs for n particles (99 n:
+ * features, moments, energies, dE/dG). */
 mdpl_status mdpl_mlp_run_floats(int64_t n, int64_t* floats_host);
 
 /* mdpl_run with the learned potential as the force field (Alg.

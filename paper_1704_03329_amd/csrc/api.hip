@@ -683,14 +683,13 @@ mdpl_status mdpl_desc_fwd(mdpl_sim* s, const double* x, const double* y, const d
 }
 
 mdpl_status mdpl_desc_bwd(mdpl_sim* s, const double* x, const double* y, const double* z,
-                          const float* dEdG, const float* mom, float* coef, float* fx, float* fy,
+                          const float* dEdG, const float* mom, float* fx, float* fy,
                           float* fz) {
-  if (!s || !x || !y || !z || !dEdG || !mom || !coef || !fx || !fy || !fz) return MDPL_EINVAL;
+  if (!s || !x || !y || !z || !dEdG || !mom || !fx || !fy || !fz) return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
-  HIP_TRY(desc_adjoint(dEdG, mom, s->n, coef, s->st));
   HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   HIP_TRY(desc_backward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm,
-                        coef, s->n, fx, fy, fz, s->st));
+                        dEdG, mom, s->n, fx, fy, fz, s->st));
   return MDPL_OK;
 }
 
@@ -783,7 +782,6 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
   float* mom = G + 24 * n;
   float* e = mom + 50 * n;
   float* dG = e + n;
-  float* coef = dG + 24 * n;
   const float rc = (float)s->p.rc;
   StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
   return run_loop(s, user, nsteps, sample_every, thermo, false,
@@ -801,9 +799,8 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
                     a.energy = e;
                     a.dEdG = dG;
                     HIP_TRY(mlp_eval(a, s->st));
-                    HIP_TRY(desc_adjoint(dG, mom, n, coef, s->st));
                     HIP_TRY(desc_backward(cur.x, cur.y, cur.z, s->cell_start, s->g, s->tl, rc,
-                                          nullptr, coef, n, (float*)cur.fx, (float*)cur.fy,
+                                          nullptr, dG, mom, n, (float*)cur.fx, (float*)cur.fy,
                                           (float*)cur.fz, s->st));
                     if (e1) {
                       HIP_TRY(hipEventRecord(e1, s->st));

@@ -118,8 +118,8 @@ __device__ __forceinline__ float ang_coef(int a, int l) {
 
 struct DescIO {
   float* G;                // n x 24 (forward output)
-  float* mom;              // n x 50 (forward output, nullable)
-  const float* coef;       // n x 68 adjoint coefficients (backward input), caller order
+  float* mom;              // n x 50 (forward output, nullable; backward input)
+  const float* dEdG;       // n x 24 (backward input), caller order
   const int32_t* perm;     // slot -> caller index (nullable: identity)
   float* fx;               // forces (backward output), caller order
   float* fy;
@@ -230,15 +230,11 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
 }
 
 // ------------------------------------------------------------- adjoint
-// coef[i] = (alpha/gamma for eta 0.5 [25], for eta 2 [25], delta_0, delta_1,
-//            dE/dG_k for the 16 radial features), all in caller order.
-__global__ void k_desc_adjoint(const float* __restrict__ dEdG, const float* __restrict__ mom,
-                               int64_t n, float* __restrict__ coef) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float* __restrict__ d = dEdG + i * kNFeat;
-  const float* __restrict__ mm = mom + i * (2 * kNMom);
-  float* __restrict__ out = coef + i * 68;
+// K = (alpha/gamma for eta 0.5 [25], for eta 2 [25], delta_0, delta_1,
+//      dE/dG_k for the 16 radial features) of one particle, from its dE/dG
+// (24) and moments (50); formed where the backward needs them.
+__device__ __forceinline__ void adjoint_coef(const float* __restrict__ d,
+                                             const float* __restrict__ mm, float out[68]) {
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     float b[5];
@@ -370,8 +366,7 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
     const double xi = x[s], yi = y[s], zi = z[s];
     const int64_t oi = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
     float Ki[68];
-#pragma unroll
-    for (int k = 0; k < 68; ++k) Ki[k] = io.coef[oi * 68 + k];
+    adjoint_coef(io.dEdG + oi * kNFeat, io.mom + oi * (2 * kNMom), Ki);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     const int ng = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
@@ -431,18 +426,11 @@ hipError_t desc_forward(const double* x, const double* y, const double* z,
   return hipGetLastError();
 }
 
-hipError_t desc_adjoint(const float* dEdG, const float* mom, int64_t n, float* coef,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_adjoint, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, dEdG, mom, n,
-                     coef);
-  return hipGetLastError();
-}
-
 hipError_t desc_backward(const double* x, const double* y, const double* z,
                          const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
-                         const int32_t* perm, const float* coef, int64_t n, float* fx, float* fy,
-                         float* fz, hipStream_t st) {
-  DescIO io{nullptr, nullptr, coef, perm, fx, fy, fz};
+                         const int32_t* perm, const float* dEdG, const float* mom, int64_t n,
+                         float* fx, float* fy, float* fz, hipStream_t st) {
+  DescIO io{nullptr, const_cast<float*>(mom), dEdG, perm, fx, fy, fz};
   hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
   const unsigned threads = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
   hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st, x, y,

@@ -196,12 +196,10 @@ hipError_t cna_signatures(const NList& nl, const int32_t* perm, int64_t n, uint3
 hipError_t desc_forward(const double* x, const double* y, const double* z,
                         const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
                         const int32_t* perm, float* G, float* mom, hipStream_t st);
-hipError_t desc_adjoint(const float* dEdG, const float* mom, int64_t n, float* coef,
-                        hipStream_t st);
 hipError_t desc_backward(const double* x, const double* y, const double* z,
                          const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
-                         const int32_t* perm, const float* coef, int64_t n, float* fx, float* fy,
-                         float* fz, hipStream_t st);
+                         const int32_t* perm, const float* dEdG, const float* mom, int64_t n,
+                         float* fx, float* fy, float* fz, hipStream_t st);
 
 struct MlpArgs;
 hipError_t mlp_eval(const MlpArgs& a, hipStream_t st);

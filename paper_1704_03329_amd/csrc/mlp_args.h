@@ -7,8 +7,8 @@ namespace mdpl {
 
 constexpr int kMlpParams = 6337;  // W1 [64][32] | b1 [64] | W2 [64][64] | b2 [64] | w3 [64] | b3
 // floats per particle of the learned-potential MD workspace:
-// G 24 | moments 50 | energy 1 | dE/dG 24 | adjoint coefficients 68
-constexpr int kMlpRunFloats = 167;
+// G 24 | moments 50 | energy 1 | dE/dG 24
+constexpr int kMlpRunFloats = 99;
 
 struct MlpArgs {
   const unsigned short* w1;  // bf16 [64][32]

@@ -266,7 +266,7 @@ class mdpl_mlp_weights(ctypes.Structure):
 
 _SIGS_MLP = {
     "mdpl_desc_fwd": ([ctypes.c_void_p] * 6, ctypes.c_int32),
-    "mdpl_desc_bwd": ([ctypes.c_void_p] * 10, ctypes.c_int32),
+    "mdpl_desc_bwd": ([ctypes.c_void_p] * 9, ctypes.c_int32),
     "mdpl_mlp_fwd": ([ctypes.POINTER(mdpl_mlp_weights), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
     "mdpl_mlp_train_floats": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
@@ -290,9 +290,9 @@ def mdpl_desc_fwd(sim, x, y, z, G, mom=None):
     _check(lib().mdpl_desc_fwd(_handle(sim), _ptr(x), _ptr(y), _ptr(z), _ptr(G), _ptr(mom)), "mdpl_desc_fwd")
 
 
-def mdpl_desc_bwd(sim, x, y, z, dEdG, mom, coef, fx, fy, fz):
-    _check(lib().mdpl_desc_bwd(_handle(sim), _ptr(x), _ptr(y), _ptr(z), _ptr(dEdG), _ptr(mom), _ptr(coef), _ptr(fx), _ptr(fy),
-                                  _ptr(fz)), "mdpl_desc_bwd")
+def mdpl_desc_bwd(sim, x, y, z, dEdG, mom, fx, fy, fz):
+    _check(lib().mdpl_desc_bwd(_handle(sim), _ptr(x), _ptr(y), _ptr(z), _ptr(dEdG), _ptr(mom), _ptr(fx), _ptr(fy),
+                               _ptr(fz)), "mdpl_desc_bwd")
 
 
 def mdpl_mlp_fwd(w: mdpl_mlp_weights, G, n, energy=None, dEdG=None):

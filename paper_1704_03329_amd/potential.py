@@ -132,7 +132,7 @@ class MLPPotential:
         def f32(*shape):
             return torch.empty(shape, dtype=torch.float32, device=self.device)
 
-        return {"G": f32(n, 24), "mom": f32(n, 50), "e": f32(n), "dG": f32(n, 24), "coef": f32(n, 68),
+        return {"G": f32(n, 24), "mom": f32(n, 50), "e": f32(n), "dG": f32(n, 24),
                 "fx": f32(n), "fy": f32(n), "fz": f32(n)}
 
     def forces(self, sim: LJSim, x, y, z, buf: dict | None = None):
@@ -143,7 +143,7 @@ class MLPPotential:
         b = buf if buf is not None else self.buffers(n)
         mdpl_desc_fwd(sim, x, y, z, b["G"], b["mom"])
         mdpl_mlp_fwd(self.weights(), b["G"], n, b["e"], b["dG"])
-        mdpl_desc_bwd(sim, x, y, z, b["dG"], b["mom"], b["coef"], b["fx"], b["fy"], b["fz"])
+        mdpl_desc_bwd(sim, x, y, z, b["dG"], b["mom"], b["fx"], b["fy"], b["fz"])
         return b["e"], b["fx"], b["fy"], b["fz"]
 
 
