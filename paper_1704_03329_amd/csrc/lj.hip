@@ -63,10 +63,10 @@ __device__ __forceinline__ double fused_kick(const ForceOut& out, int64_t s, dou
 // MT: arithmetic type of the pair force; OT: stored force type.  The pair
 // force is accumulated in FP64 (one conversion of the scalar factor per pair
 // instead of three of the separation).
-// The plain pass asks for 8 waves per SIMD (<= 64 VGPRs), so that two
+// Both passes ask for 8 waves per SIMD (<= 64 VGPRs), so that two
 // 1024-thread workgroups (LDS: two tiles) share a CU.
 template <typename MT, typename OT, bool ENERGY>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ENERGY ? 1 : 8)))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
                 const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g, TileList tl,
                 LJConst c, ForceOut out) {
@@ -82,9 +82,8 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
   double e = 0.0, w = 0.0, ke = 0.0;
-  // the plain pass gives each particle two lanes, each taking every other
-  // list word (more waves in flight); the energy pass one lane
-  constexpr int LPP = ENERGY ? 1 : 2;
+  // two lanes per particle, each taking every other list word (more waves in flight)
+  constexpr int LPP = 2;
   const int part = (int)threadIdx.x % LPP;
   for (int s = s0 + (int)threadIdx.x / LPP; s < s1; s += (int)blockDim.x / LPP) {
     const double xi = x[s], yi = y[s], zi = z[s];
@@ -149,6 +148,7 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
       ax += __shfl_xor(ax, 1, 64);
       ay += __shfl_xor(ay, 1, 64);
       az += __shfl_xor(az, 1, 64);
+      if (ENERGY) ei += __shfl_xor(ei, 1, 64);
       if (part) continue;
     }
     if (out.fuse) {
@@ -206,8 +206,7 @@ static void launch_force(bool energy, hipStream_t st, const double* x, const dou
   const dim3 grid(tile_grid_blocks(g.nbricks));
   const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
   if (energy)
-    hipLaunchKernelGGL((k_lj_force<MT, OT, true>), grid, dim3(tl.threads), 0, st, x, y, z, cs, g, tl,
-                       c, out);
+    hipLaunchKernelGGL((k_lj_force<MT, OT, true>), grid, dim3(two), 0, st, x, y, z, cs, g, tl, c, out);
   else
     hipLaunchKernelGGL((k_lj_force<MT, OT, false>), grid, dim3(two), 0, st, x, y, z, cs, g, tl, c,
                        out);
