@@ -340,8 +340,8 @@ def main():
                         "positions/energy/virial, PE+virial every 10 steps",
             "n_atoms": n,
             "nlist_entries_per_atom": entries / n,
-            "precision": "FP32 pair force math and sums; FP64 positions, velocities, separations, "
-                         "cutoff test, energy, virial",
+            "precision": "FP32 pair force factor, forces stored as FP32; FP64 positions, velocities, "
+                         "separations, cutoff test, per-particle force sums, energy, virial",
         },
         "roofline": {
             "bound": "hbm",

@@ -62,14 +62,16 @@ struct RowScan {
 // Candidates u = ub, ub + K, ... < ue (one contiguous range of tile
 // indices), UNROLL at a time so that their LDS loads overlap; slots past the
 // end read the far-away dummy.  One LDS atomic reserves the ranks of all
-// accepted candidates of a step.
+// accepted candidates of a step; each candidate's offset among them is
+// known before it, so a store needs one comparison with the capacity.
 template <int UNROLL>
 __device__ __forceinline__ void scan_range(const TileShared32& t, int ub, int ue,
                                            const RowScan& q) {
   for (int u0 = ub; u0 < ue; u0 += UNROLL * q.K) {
+    constexpr uint32_t kNone = 1u << 20;  // offset of a rejected candidate: past any list
     int uu[UNROLL];
-    bool acc[UNROLL];
-    int na = 0;
+    uint32_t rank[UNROLL];  // offset among this step's accepted candidates, or kNone
+    uint32_t na = 0;
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
       const int u = u0 + j * q.K;
@@ -80,25 +82,24 @@ __device__ __forceinline__ void scan_range(const TileShared32& t, int ub, int ue
       const float dx = q.xi - t.x[uu[j]], dy = q.yi - t.y[uu[j]], dz = q.zi - t.z[uu[j]];
       const float d2f = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
       const bool other = uu[j] != q.self;
-      acc[j] = other && d2f < q.r2lo;
+      bool acc = other && d2f < q.r2lo;
       if (other && !(d2f < q.r2lo) && d2f <= q.r2hi) {
         // inside the guard band: the definition decides
         const int c = tile_cell_of(t, q.ntc, uu[j]);
         const int sj = t.src[c] + (uu[j] - t.prefix[c]);
-        acc[j] = exact_d2(q.xs, q.ys, q.zs, q.x[sj], q.y[sj], q.z[sj], q.Lx, q.Ly, q.Lz, q.hx, q.hy,
-                          q.hz) < q.r2;
+        acc = exact_d2(q.xs, q.ys, q.zs, q.x[sj], q.y[sj], q.z[sj], q.Lx, q.Ly, q.Lz, q.hx, q.hy,
+                       q.hz) < q.r2;
       }
-      na += acc[j] ? 1 : 0;
+      rank[j] = acc ? na : kNone;
+      na += acc ? 1u : 0u;
     }
     if (na) {
-      uint32_t m = (uint32_t)atomicAdd(q.cnt, na);
+      const uint32_t m = (uint32_t)atomicAdd(q.cnt, (int)na);
 #pragma unroll
       for (int j = 0; j < UNROLL; ++j) {
-        if (acc[j]) {
-          if (m < (uint32_t)q.max_nb)
-            q.base[(uint64_t)(m >> 2) * q.stride4 + (m & 3u)] = (uint16_t)(uu[j] << 3);
-          ++m;
-        }
+        const uint32_t mj = m + rank[j];
+        if (mj < (uint32_t)q.max_nb)
+          q.base[(uint64_t)(mj >> 2) * q.stride4 + (mj & 3u)] = (uint16_t)(uu[j] << 3);
       }
     }
   }
@@ -208,11 +209,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     }
   }
   __syncthreads();
+  // every slot of the brick gets its count (zero past kBrickMax, flagged above)
   int most = 0;
-  const int nb = nbrick < kBrickMax ? nbrick : kBrickMax;
-  for (int la = threadIdx.x; la < nb; la += blockDim.x) {
+  for (int la = threadIdx.x; la < nbrick; la += blockDim.x) {
     const int s = s0 + la;
-    const int count = acnt[la];
+    const int count = la < kBrickMax ? acnt[la] : 0;
     const int kept = count < max_nb ? count : max_nb;
     for (int m = kept; m < ((kept + 3) & ~3); ++m)  // pad the last word
       half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(kTileDummy << 3);

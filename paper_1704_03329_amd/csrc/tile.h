@@ -123,15 +123,16 @@ __device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
   __syncthreads();
 }
 
-// Tile cell of tile particle u < total (binary search over the prefix).
+// Tile cell of tile particle u < total (binary search over the prefix;
+// a tile has at least 27 cells, so the first halving always happens).
 template <typename TS>
 __device__ __forceinline__ int tile_cell_of(const TS& t, int ntc, int u) {
   int lo = 0, hi = ntc;  // prefix[lo] <= u < prefix[hi]
-  while (hi - lo > 1) {
+  do {
     const int mid = (lo + hi) >> 1;
     if (t.prefix[mid] <= u) lo = mid;
     else hi = mid;
-  }
+  } while (hi - lo > 1);
   return lo;
 }
 
