@@ -77,8 +77,9 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
   const int total = tile_cells(g, brick, cs, t);
   tile_load<true>(g, x, y, z, total, t);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
-  const MT sig2 = (MT)c.sigma2;
-  const MT c48 = (MT)(48.0 * c.eps), c24 = (MT)(24.0 * c.eps);
+  // plain pass: f_ij / dr_ij = x^4 (A x^3 - B) with x = 1 / d2, A = 48 eps s^12, B = 24 eps s^6
+  const double sig6 = c.sigma2 * c.sigma2 * c.sigma2;
+  const MT fa = (MT)(48.0 * c.eps * sig6 * sig6), fb = (MT)(24.0 * c.eps * sig6);
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
   double e = 0.0, w = 0.0, ke = 0.0;
@@ -101,12 +102,22 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
     for (int gi = part; gi < ngroups; gi += LPP) {
       const uint64_t word = next;
       if (gi + LPP < ngroups) next = col[(int64_t)(gi + LPP) * tl.stride];
+      // FP32 plain pass: entry k + 1's tile position is read while entry k is
+      // computed (the other variants have no registers to spare for it)
+      constexpr bool kAhead = !ENERGY && sizeof(MT) == 4;
+      double qx, qy, qz;
+      auto tile_pos = [&](int k) {
+        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;  // byte offset in a tile array
+        qx = *(const double*)((const char*)t.x + off);
+        qy = *(const double*)((const char*)t.y + off);
+        qz = *(const double*)((const char*)t.z + off);
+      };
+      tile_pos(0);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;  // byte offset in a tile array
-        const double dx = xi - *(const double*)((const char*)t.x + off);
-        const double dy = yi - *(const double*)((const char*)t.y + off);
-        const double dz = zi - *(const double*)((const char*)t.z + off);
+        if (!kAhead && k > 0) tile_pos(k);
+        const double dx = xi - qx, dy = yi - qy, dz = zi - qz;
+        if (kAhead && k < 3) tile_pos(k + 1);
         double g;
         if (ENERGY) {
           // pair energy and virial in FP64 on the sampled steps
@@ -133,9 +144,8 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
           } else {
             inv = 1.0 / d2;
           }
-          const MT s2 = sig2 * inv;
-          const MT s6 = s2 * s2 * s2;
-          MT gg = inv * s6 * (c48 * s6 - c24);
+          const MT x2 = inv * inv;
+          MT gg = (x2 * x2) * (fa * (x2 * inv) - fb);
           if constexpr (sizeof(MT) != 4) gg = in ? gg : (MT)0;
           g = (double)gg;
         }
