@@ -133,6 +133,28 @@ def test_capacity_overflow_flagged():
     assert st == C.MDPL_ECAPACITY and flags & C.FLAG_NL_OVERFLOW and maxc == 80
 
 
+def test_dense_brick_overflow_flagged():
+    """1100 atoms packed inside one cell of a dilute box: the brick that holds
+    them has more particles than the list builder counts per brick.  The
+    build must flag it (and the per-particle overflow), give every slot a
+    count within the capacity, and the force pass must still run."""
+    from paper_1704_03329_amd import mdpl as C
+
+    L = 20.0  # 7 cells of 2.857 per axis; 3100 atoms -> bricks of 3^3 cells
+    box = np.array([L, L, L])
+    cluster = 9.0 + 1.6 * mdinputs.random_box(1100, [1.0, 1.0, 1.0], 41)  # inside cell (3, 3, 3)
+    pos = np.concatenate([mdinputs.random_box(2000, box, 42), cluster])
+    n = pos.shape[0]
+    sim = _sim(n, box, rc=2.5, skin=0.3, max_nb=128)
+    cols = split_dev(pos)
+    sim.build(*cols)
+    st, flags, _ = sim.check(raise_on_error=False)
+    assert st == C.MDPL_ECAPACITY and flags & C.FLAG_NL_OVERFLOW
+    assert 0 < C.mdpl_nlist_entries(sim.handle) <= n * 128
+    sim.forces(*cols, energy=True)
+    torch.cuda.synchronize()
+
+
 def _run(sim, pos, vel, nsteps, every):
     state = sim.new_state(torch.from_numpy(pos), torch.from_numpy(vel))
     thermo = sim.run(state, nsteps, every)
