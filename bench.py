@@ -248,6 +248,10 @@ def main():
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
     ap.add_argument("--mlp-steps", type=int, default=6000)
+    ap.add_argument("--newton", action="store_true",
+                    help="time the run with half lists (each pair once, reactions by atomics)")
+    ap.add_argument("--no-newton-compare", action="store_true",
+                    help="skip the short half-list run reported beside the main one")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one elementwise copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -277,49 +281,58 @@ def main():
     n = d["pos"].shape[0]
     box = d["box"]
     log(f"N={n} box={box[0]:.4f} building context")
-    sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp32", shift="cutoff",
-                max_nb=128)
-    state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
-    torch.cuda.synchronize()
+    def timed_run(newton, warmup, steps):
+        sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp32", shift="cutoff",
+                    max_nb=128, newton=newton)
+        state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+        torch.cuda.synchronize()
+        log(f"{'half' if newton else 'full'} lists: warmup {warmup} steps")
+        sim.run(state, warmup, 10)
+        torch.cuda.synchronize()
+        st, flags, _ = sim.check(raise_on_error=False)
+        if st != 0:
+            raise SystemExit(f"warmup flagged status {st} flags {flags}")
+        C.mdpl_set_timing(sim.handle, True)
+        C.mdpl_kernel_time(sim.handle, 0)  # reset
+        C.mdpl_kernel_time(sim.handle, 1)
+        log(f"timing {steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        thermo = sim.run(state, steps, 10)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        st, flags, _ = sim.check(raise_on_error=False)
+        if st != 0:
+            raise SystemExit(f"timed run flagged status {st} flags {flags}")
+        f_ms, f_n = C.mdpl_kernel_time(sim.handle, 0)
+        fe_ms, fe_n = C.mdpl_kernel_time(sim.handle, 1)
+        C.mdpl_set_timing(sim.handle, False)
+        entries = C.mdpl_nlist_entries(sim.handle)
+        log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
+            f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}")
+        return dict(elapsed=elapsed, thermo=thermo.cpu().numpy(), f_ms=f_ms, f_n=f_n, fe_ms=fe_ms, fe_n=fe_n,
+                    entries=entries)
 
-    log(f"warmup {args.warmup} steps")
-    sim.run(state, args.warmup, 10)
-    torch.cuda.synchronize()
-    st, flags, maxc = sim.check(raise_on_error=False)
-    if st != 0:
-        raise SystemExit(f"warmup flagged status {st} flags {flags}")
-
-    C.mdpl_set_timing(sim.handle, True)
-    C.mdpl_kernel_time(sim.handle, 0)  # reset
-    C.mdpl_kernel_time(sim.handle, 1)
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    thermo = sim.run(state, args.steps, 10)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    st, flags, maxc = sim.check(raise_on_error=False)
-    if st != 0:
-        raise SystemExit(f"timed run flagged status {st} flags {flags}")
-    f_ms, f_n = C.mdpl_kernel_time(sim.handle, 0)
-    fe_ms, fe_n = C.mdpl_kernel_time(sim.handle, 1)
-    C.mdpl_set_timing(sim.handle, False)
-    entries = C.mdpl_nlist_entries(sim.handle)
-    th = thermo.cpu().numpy()
+    r = timed_run(args.newton, args.warmup, args.steps)
+    elapsed, th, entries = r["elapsed"], r["thermo"], r["entries"]
+    f_ms, f_n, fe_ms, fe_n = r["f_ms"], r["f_n"], r["fe_ms"], r["fe_n"]
     etot = th[:, 0] + th[:, 1]
-    log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
-        f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}")
 
-    # algorithmic bytes of one plain force launch, which in the run also applies
-    # the velocity-Verlet kick-kick-drift of the next step: per atom cnt (4) +
-    # own position (24, also the neighbour positions, each read once) +
-    # velocity read and written (48) + new position written (24); per list
-    # entry its 16-bit tile offset (2)
-    alg_bytes = n * (4 + 24 + 48 + 24) + 2 * entries
+    if args.newton:
+        # the half-list force pass (timed with the clearing of the outputs): per
+        # atom cnt (4) + own position (24, also the neighbour positions) + its
+        # force (12, added by atomics); per list entry its 16-bit tile offset (2)
+        alg_bytes = n * (4 + 24 + 12) + 2 * entries
+    else:
+        # algorithmic bytes of one plain force launch, which in the run also
+        # applies the velocity-Verlet kick-kick-drift of the next step: per atom
+        # cnt (4) + own position (24, also the neighbour positions, each read
+        # once) + velocity read and written (48) + new position written (24);
+        # per list entry its 16-bit tile offset (2)
+        alg_bytes = n * (4 + 24 + 48 + 24) + 2 * entries
     avg_s = (f_ms / 1e3) / max(f_n, 1)
     achieved = alg_bytes / avg_s / 1e9
-    traffic = measured_traffic()
+    traffic = None if args.newton else measured_traffic()
 
     out = {
         "metric": METRIC,
@@ -338,6 +351,8 @@ def main():
             "workload": f"LJ fluid N={n} ({n_side}^3 sc lattice, rho 0.8442, T*=1, seed 2), rc 2.5, "
                         "skin 0.3, rebuild every 10 steps, dt 0.001, FP32 pair forces, FP64 "
                         "positions/energy/virial, PE+virial every 10 steps",
+            "neighbour_lists": "half (each pair once, reactions by atomics)" if args.newton
+                               else "full (every ordered pair)",
             "n_atoms": n,
             "nlist_entries_per_atom": entries / n,
             "precision": "FP32 pair force factor, forces stored as FP32; FP64 positions, velocities, "
@@ -345,7 +360,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_lj_force<float,float,false> (with the fused kick-kick-drift)",
+            "kernel": ("k_lj_force_half<float,float,false,false> (with the clearing of the forces)"
+                       if args.newton else "k_lj_force<float,float,false> (with the fused kick-kick-drift)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -362,6 +378,20 @@ def main():
         "energy_drift_per_atom": float(np.max(np.abs(etot - etot[0])) / n),
         "hbm_gbs_force": achieved,
     }
+    if not args.newton and not args.no_newton_compare:
+        # the same workload with half lists (Newton's third law), a shorter run
+        h = timed_run(True, min(args.warmup, 20), min(args.steps, 200))
+        hs = min(args.steps, 200)
+        out["half_lists"] = {
+            "value": n * hs / h["elapsed"],
+            "unit": "atom-steps/s",
+            "steps": hs,
+            "ms_per_step": h["elapsed"] / hs * 1e3,
+            "force_us": h["f_ms"] / max(h["f_n"], 1) * 1e3,
+            "force_energy_virial_us": h["fe_ms"] / max(h["fe_n"], 1) * 1e3,
+            "nlist_entries_per_atom": h["entries"] / n,
+            "note": "force pass timed with the clearing of the outputs; the kicks run as their own pass",
+        }
     if not args.no_mlp:
         out["mlp_vs_lj"] = mlp_report(args)
     if not args.no_analysis:

@@ -82,6 +82,12 @@ typedef struct {
   int32_t shift;      /* MDPL_SHIFT_* */
   int32_t precision;  /* MDPL_FP64 or MDPL_FP32 */
   int32_t max_nb;     /* neighbour-list capacity per particle (1 .. 1024) */
+  int32_t newton;     /* 0: full lists, every ordered pair (the pair loop of Sec. 2 over all
+                         j != i); 1: half lists, each pair once with the reaction -f_ij
+                         applied to j (Newton's third law; Sec. 2, the comment on it beside
+                         the pair loop): forces are summed with atomics, so their last
+                         bits vary from run to run, and the learned-potential entry points
+                         reject such a sim (MDPL_EINVAL) */
 } mdpl_lj_params;
 
 typedef struct mdpl_sim mdpl_sim;
@@ -117,7 +123,8 @@ mdpl_status mdpl_sim_destroy(mdpl_sim* sim);
 mdpl_status mdpl_build(mdpl_sim* sim, const double* x, const double* y, const double* z);
 
 /* Copy the list of the last mdpl_build as directed pairs (i, j) in the
- * caller's particle indices, unordered.  Writes min(count, cap) pairs,
+ * caller's particle indices, unordered (with newton = 1 each pair appears
+ * once, in one direction).  Writes min(count, cap) pairs,
  * returns the total in *count_host.  Synchronises the stream. */
 mdpl_status mdpl_nlist_export(mdpl_sim* sim, int32_t* i_out, int32_t* j_out, int64_t cap,
                               int64_t* count_host);

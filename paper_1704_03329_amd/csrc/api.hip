@@ -101,22 +101,26 @@ mdpl_status validate(const mdpl_lj_params* p) {
   if (p->shift < 0 || p->shift > 2) return MDPL_EINVAL;
   if (p->precision != MDPL_FP64 && p->precision != MDPL_FP32) return MDPL_EINVAL;
   if (p->max_nb < 1 || p->max_nb > 1024) return MDPL_EINVAL;
+  if (p->newton != 0 && p->newton != 1) return MDPL_EINVAL;
   Grid g;
   int unit[3] = {1, 1, 1};
   return make_grid(p->box, p->rc + p->skin, unit, &g);
 }
 
 // Brick of cells handled by one workgroup of the LJ kernels: the largest
-// cube (3, 2 or 1 cells) whose tile, (B+2)^3 cells at the mean occupancy,
-// fills at most 85% of the LDS tile; workgroup size ~1.15x its particles.
+// cube (3, 2 or 1 cells) whose tile at the mean occupancy fills at most 85%
+// of the LDS tile ((B+2)^3 cells; with half lists the cells from the brick's
+// first one on, of a smaller tile, at most 90%); workgroup size ~1.15x its
+// particles.
 void lj_grid(const mdpl_lj_params* p, Grid* g, int* threads) {
   int unit[3] = {1, 1, 1};
   make_grid(p->box, p->rc + p->skin, unit, g);
   const double per_cell = (double)p->n / ((double)g->nc[0] * g->nc[1] * g->nc[2]);
   int b = 1;
   for (int cand = 3; cand >= 1; --cand) {
-    const double tile = (cand + 2.0) * (cand + 2.0) * (cand + 2.0) * per_cell;
-    if (tile <= 0.85 * kTileMax) {
+    const int w = cand + 2, cells = p->newton ? w * w * w - ((w + 1) * w + 1) : w * w * w;
+    const double tile = cells * per_cell;
+    if (p->newton ? tile <= 0.9 * (kTileMaxHalf - 1) : tile <= 0.85 * kTileMax) {
       b = cand;
       break;
     }
@@ -201,7 +205,7 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
     HIP_TRY(hipEventRecord(e0, s->st));
   }
   int nb = 0;
-  HIP_TRY(lj_force(x, y, z, s->cell_start, s->g, s->tl, s->c, kind, energy, out, s->st, &nb));
+  HIP_TRY(lj_force(x, y, z, s->cell_start, s->g, s->tl, s->c, kind, energy, out, s->n, s->st, &nb));
   if (e1) {
     HIP_TRY(hipEventRecord(e1, s->st));
     s->tm.ev[timing_slot].push_back(e0);
@@ -285,6 +289,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->tl.cnt = take<int32_t>(w, 4 * (size_t)s->npad);
   s->tl.stride = s->npad;
   s->tl.max_nb = p->max_nb;
+  s->tl.half = p->newton;
   s->tl.threads = threads;
   s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
   s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
@@ -383,7 +388,7 @@ mdpl_status mdpl_lj_backward(mdpl_sim* s, const double* x, const double* y, cons
   // FP64 arithmetic for the FP64 context, FP32 pair math for the FP32 one;
   // the gradient is stored in double either way
   const int kind = s->p.precision == MDPL_FP64 ? 2 : 3;
-  HIP_TRY(lj_force(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, s->c, kind, false, out, s->st,
+  HIP_TRY(lj_force(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, s->c, kind, false, out, s->n, s->st,
                    nullptr));
   return MDPL_OK;
 }
@@ -563,7 +568,8 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
   const int prec = s->p.precision;
   StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
-  return run_loop(s, user, nsteps, sample_every, thermo, true,
+  // with half lists a force is complete only when its pass has ended: no fused kicks
+  return run_loop(s, user, nsteps, sample_every, thermo, !s->tl.half,
                   [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool fuse,
                       double* const* spare, double* ke) {
                     return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr,
@@ -674,7 +680,7 @@ mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t 
 // ------------------------------------------------------- learned potential
 mdpl_status mdpl_desc_fwd(mdpl_sim* s, const double* x, const double* y, const double* z, float* G,
                           float* mom) {
-  if (!s || !x || !y || !z || !G) return MDPL_EINVAL;
+  if (!s || !x || !y || !z || !G || s->tl.half) return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
   HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   HIP_TRY(desc_forward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm, G,
@@ -685,7 +691,7 @@ mdpl_status mdpl_desc_fwd(mdpl_sim* s, const double* x, const double* y, const d
 mdpl_status mdpl_desc_bwd(mdpl_sim* s, const double* x, const double* y, const double* z,
                           const float* dEdG, const float* mom, float* fx, float* fy,
                           float* fz) {
-  if (!s || !x || !y || !z || !dEdG || !mom || !fx || !fy || !fz) return MDPL_EINVAL;
+  if (!s || !x || !y || !z || !dEdG || !mom || !fx || !fy || !fz || s->tl.half) return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
   HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   HIP_TRY(desc_backward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm,
@@ -775,7 +781,7 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
   if (!s || !mlp_ok(w) || !ws || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids)
     return MDPL_EINVAL;
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
-  if (s->p.precision != MDPL_FP32) return MDPL_EINVAL;
+  if (s->p.precision != MDPL_FP32 || s->tl.half) return MDPL_EINVAL;
   const int64_t n = s->n;
   if (ws_floats < (int64_t)kMlpRunFloats * n) return MDPL_EWORKSPACE;
   float* G = ws;

@@ -119,12 +119,14 @@ constexpr int kBrickMax = 1024;             // particles of one brick the list b
 constexpr int kTileDummy = kTileMax - 1;    // padding slot
 constexpr int kTileCap = kTileMax - 1;      // particles a tile can hold
 constexpr int kTileCells = 125;             // B <= 3 per axis
+constexpr int kTileMaxHalf = 2144;          // tile slots of a half-list tile (LDS)
 struct TileList {
   uint64_t* nbr;
   int32_t* cnt;     // clamped to max_nb
   int64_t stride;   // words per group row (>= n)
   int max_nb;       // multiple of 4
   int threads;      // workgroup size of the tile kernels
+  int half;         // 1: each pair once (Newton's third law), tiles of kTileMaxHalf slots
 };
 hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
                             const int32_t* skeys, const int32_t* cell_start, const Grid& g,
@@ -158,7 +160,7 @@ struct ForceOut {
 // Partials are written per brick (nblocks_out = number of bricks).
 hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,
                     const Grid& g, const TileList& tl, const LJConst& c, int precision, bool energy,
-                    const ForceOut& out, hipStream_t st, int* nblocks_out);
+                    const ForceOut& out, int64_t n, hipStream_t st, int* nblocks_out);
 
 // Velocity Verlet particle loops on the sorted state (INC on v and r).
 //   mode 0: v += h F ; r += dt v                          (first step)

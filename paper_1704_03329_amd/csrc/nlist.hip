@@ -12,7 +12,10 @@
 //  * the LJ list: one workgroup per brick stages its tile (stored positions,
 //    no images) in LDS, one wave per home cell tests the 27 tile cells of its
 //    stencil; entries are 16-bit tile byte offsets, column-major, so the force
-//    pass reads one coalesced word per four neighbours;
+//    pass reads one coalesced word per four neighbours.  A half list (each
+//    pair once, Newton's third law) keeps j in the list of i only if j's tile
+//    index is larger (tile.h): four of the nine stencil rows whole, and the
+//    row of i's cell from i on;
 //  * the analysis list (bond order / CNA): one thread per particle walks the
 //    9 rows of 3 consecutive cells in global memory, entries are sorted-slot
 //    indices, row-major so a whole list is one contiguous read.
@@ -64,9 +67,8 @@ struct RowScan {
 // end read the far-away dummy.  One LDS atomic reserves the ranks of all
 // accepted candidates of a step; each candidate's offset among them is
 // known before it, so a store needs one comparison with the capacity.
-template <int UNROLL>
-__device__ __forceinline__ void scan_range(const TileShared32& t, int ub, int ue,
-                                           const RowScan& q) {
+template <int UNROLL, typename TS>
+__device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const RowScan& q) {
   for (int u0 = ub; u0 < ue; u0 += UNROLL * q.K) {
     constexpr uint32_t kNone = 1u << 20;  // offset of a rejected candidate: past any list
     int uu[UNROLL];
@@ -75,7 +77,7 @@ __device__ __forceinline__ void scan_range(const TileShared32& t, int ub, int ue
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
       const int u = u0 + j * q.K;
-      uu[j] = u < ue ? u : kTileDummy;
+      uu[j] = u < ue ? u : TS::kDummy;
     }
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
@@ -106,19 +108,20 @@ __device__ __forceinline__ void scan_range(const TileShared32& t, int ub, int ue
 }
 
 // One wave per home cell (up to 16 per workgroup); at most 64 VGPRs so that
-// two 1024-thread workgroups share a CU.
+// two 1024-thread workgroups share a CU.  TS: the tile (full or half list).
+template <typename TS, bool HALF>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_build_tile_nlist(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
     float guard, TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
-  __shared__ TileShared32 t;
+  __shared__ TS t;
   __shared__ int acnt[kBrickMax];
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
-  const int total = tile_cells(g, brick, cs, t);
+  const int total = tile_cells(g, brick, cs, t, HALF);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const int nbrick = s1 - s0;
-  if (threadIdx.x == 0 && (total > kTileCap || nbrick > kBrickMax))
+  if (threadIdx.x == 0 && (total > TS::kCap || nbrick > kBrickMax))
     atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
   for (int a = threadIdx.x; a < kBrickMax; a += blockDim.x) acnt[a] = 0;
   const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
@@ -131,11 +134,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   const double oy = (double)(by * g.B[1] - 1) * (Ly / g.nc[1]);
   const double oz = (double)(bz * g.B[2] - 1) * (Lz / g.nc[2]);
   {
-    const int nt = total < kTileCap ? total : kTileCap;
+    const int nt = total < TS::kCap ? total : TS::kCap;
     if (threadIdx.x == 0) {
-      t.x[kTileDummy] = kFarF;
-      t.y[kTileDummy] = kFarF;
-      t.z[kTileDummy] = kFarF;
+      t.x[TS::kDummy] = kFarF;
+      t.y[TS::kDummy] = kFarF;
+      t.z[TS::kDummy] = kFarF;
     }
     for (int u = threadIdx.x; u < nt; u += blockDim.x) {
       const int c = tile_cell_of(t, ntc, u);
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       const int self = t.prefix[tc0] + a;
       const int s = slot0 + a;          // sorted slot of particle a
       const int la = s - s0;            // its index within the brick
-      const bool ok = active && self < kTileCap && la >= 0 && la < kBrickMax && s < s1;
+      const bool ok = active && self < TS::kCap && la >= 0 && la < kBrickMax && s < s1;
       RowScan q;
       q.xi = ok ? t.x[self] : 0.0f;
       q.yi = ok ? t.y[self] : 0.0f;
@@ -201,9 +204,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           // a stencil row: three consecutive tile cells, one contiguous index range
           const int tcl = tc0 + oz * TXY + oy2 * TX - 1;
           if (!ok) continue;
+          // half list: only tile indices past the particle's own (rows below it are empty)
+          if (HALF && (oz < 0 || (oz == 0 && oy2 < 0))) continue;
+          int ub = t.prefix[tcl];
+          if (HALF && ub <= self) ub = self + 1;
           int ue = t.prefix[tcl + 3];
-          ue = ue < kTileCap ? ue : kTileCap;
-          scan_range<4>(t, t.prefix[tcl] + k, ue, q);
+          ue = ue < TS::kCap ? ue : TS::kCap;
+          scan_range<4>(t, ub + k, ue, q);
         }
       }
     }
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const int count = la < kBrickMax ? acnt[la] : 0;
     const int kept = count < max_nb ? count : max_nb;
     for (int m = kept; m < ((kept + 3) & ~3); ++m)  // pad the last word
-      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(kTileDummy << 3);
+      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(TS::kDummy << 3);
     tl.cnt[s] = kept;
     if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
     most = count > most ? count : most;
@@ -244,8 +251,13 @@ hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
   const double rext = sqrt(r2);
   const double err = 2.0 * sqrt(3.0) * rext * u32 * (2.0 * span + 2.0 * rext) + 3.0 * u32 * r2;
   const float guard = (float)(8.0 * err);
-  hipLaunchKernelGGL(k_build_tile_nlist, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st,
-                     x, y, z, skeys, cell_start, g, r2, guard, tl, flags, maxcount);
+  const dim3 grid(tile_grid_blocks(g.nbricks));
+  if (tl.half)
+    hipLaunchKernelGGL((k_build_tile_nlist<TileHalf32, true>), grid, dim3(threads), 0, st, x, y, z,
+                       skeys, cell_start, g, r2, guard, tl, flags, maxcount);
+  else
+    hipLaunchKernelGGL((k_build_tile_nlist<TileShared32, false>), grid, dim3(threads), 0, st, x, y,
+                       z, skeys, cell_start, g, r2, guard, tl, flags, maxcount);
   return hipGetLastError();
 }
 
@@ -255,10 +267,10 @@ __global__ __launch_bounds__(1024) void k_export_tile_pairs(
     TileList tl, const int32_t* __restrict__ cs, Grid g, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ offsets, int32_t* __restrict__ i_out, int32_t* __restrict__ j_out,
     int64_t cap) {
-  __shared__ TileShared t;
+  __shared__ TileCells t;
   const int brick = brick_of_block(g.nbricks);
   if (brick >= g.nbricks) return;
-  tile_cells(g, brick, cs, t);
+  tile_cells(g, brick, cs, t, tl.half != 0);
   const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
@@ -268,12 +280,7 @@ __global__ __launch_bounds__(1024) void k_export_tile_pairs(
     for (int m = 0; m < c; ++m) {
       if (o + m >= cap) break;
       const int u = (int)((tl.nbr[(int64_t)(m >> 2) * tl.stride + s] >> (16 * (m & 3))) & 0xffff) >> 3;
-      int lo = 0, hi = ntc;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (t.prefix[mid] <= u) lo = mid;
-        else hi = mid;
-      }
+      const int lo = tile_cell_of(t, ntc, u);
       i_out[o + m] = pi;
       j_out[o + m] = perm[t.src[lo] + (u - t.prefix[lo])];
     }

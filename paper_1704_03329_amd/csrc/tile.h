@@ -11,6 +11,16 @@
 // image (-1, 0, +1 per axis) so that a tile may be filled either with the
 // stored positions (exact minimum-image tests) or with the image positions
 // (plain differences, no per-pair image arithmetic).
+//
+// Half lists (each pair once) list j for i when j's tile index is larger:
+// tile indices run z, y, x lexicographically, so that is the case when j's
+// cell is one of the 13 "upper" neighbours of i's cell (offset (ox, oy, oz)
+// with oz > 0, or oz = 0 and oy > 0, or oz = oy = 0 and ox > 0) or the same
+// cell at a later slot.  The rule depends on the offset only, so the pair
+// (i, j) is listed by exactly one of its particles whatever bricks and
+// periodic images hold them.  Such a tile needs only the cells from the
+// brick's first cell on (94 of 125 for 3^3 bricks); the others are left
+// empty.
 #pragma once
 
 #include "device_util.h"
@@ -18,17 +28,31 @@
 
 namespace mdpl {
 
-template <typename T>
+template <typename T, int CAP>
 struct TileOf {
-  T x[kTileMax];
-  T y[kTileMax];
-  T z[kTileMax];
+  static constexpr int kSlots = CAP;
+  static constexpr int kDummy = CAP - 1;  // padding slot
+  static constexpr int kCap = CAP - 1;    // particles a tile can hold
+  T x[CAP];
+  T y[CAP];
+  T z[CAP];
   int prefix[kTileCells + 1];
   int src[kTileCells];
   int code[kTileCells];
 };
-using TileShared = TileOf<double>;  // FP64 image positions (force and descriptor passes)
-using TileShared32 = TileOf<float>; // FP32 positions relative to the tile origin (list build)
+// the cell table alone (kernels that map tile indices to slots only)
+struct TileCells {
+  int prefix[kTileCells + 1];
+  int src[kTileCells];
+  int code[kTileCells];
+};
+// full lists: FP64 image positions (force and descriptor passes) and FP32
+// positions relative to the tile origin (list build)
+using TileShared = TileOf<double, kTileMax>;
+using TileShared32 = TileOf<float, kTileMax>;
+// half lists: the same with the capacity of a half tile
+using TileHalf = TileOf<double, kTileMaxHalf>;
+using TileHalf32 = TileOf<float, kTileMaxHalf>;
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // run of bricks (a slab of the box) so that tile reloads hit its own L2.
@@ -46,14 +70,17 @@ __device__ __forceinline__ void brick_coords(const Grid& g, int brick, int& bx, 
 }
 
 // Fills prefix/src/code for the tile of `brick`; returns the particle count
-// (possibly above kTileMax).  Ends with a barrier.
+// (possibly above the tile's capacity).  half: the cells before the brick's
+// first cell are left empty.  Ends with a barrier.
 template <typename TS>
-__device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __restrict__ cs, TS& t) {
+__device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __restrict__ cs, TS& t,
+                                 bool half = false) {
   const int TX = g.B[0] + 2, TY = g.B[1] + 2, TZ = g.B[2] + 2;
   const int ntc = TX * TY * TZ;
   int bx, by, bz;
   brick_coords(g, brick, bx, by, bz);
   const int ox = bx * g.B[0] - 1, oy = by * g.B[1] - 1, oz = bz * g.B[2] - 1;
+  const int first = half ? (TY + 1) * TX + 1 : 0;  // tile index of the brick's first cell
   for (int tc = threadIdx.x; tc < ntc; tc += blockDim.x) {
     const int lx = tc % TX, ly = (tc / TX) % TY, lz = tc / (TX * TY);
     int cx = ox + lx, cy = oy + ly, cz = oz + lz;
@@ -64,7 +91,7 @@ __device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __rest
     const int key = cell_key(g, cx, cy, cz);
     const int b = cs[key];
     t.src[tc] = b;
-    t.prefix[tc + 1] = cs[key + 1] - b;
+    t.prefix[tc + 1] = tc < first ? 0 : cs[key + 1] - b;
     t.code[tc] = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4);
   }
   if (threadIdx.x == 0) t.prefix[0] = 0;
@@ -88,18 +115,18 @@ __device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __rest
   return t.prefix[ntc];
 }
 
-// Copies the tile's positions (at most kTileCap) into LDS; IMAGE adds the
+// Copies the tile's positions (at most TS::kCap) into LDS; IMAGE adds the
 // periodic image offsets.  Ends with a barrier.
-template <bool IMAGE>
+template <bool IMAGE, typename TS>
 __device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
                                  const double* __restrict__ y, const double* __restrict__ z,
-                                 int total, TileShared& t) {
+                                 int total, TS& t) {
   const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
-  const int nt = total < kTileCap ? total : kTileCap;
+  const int nt = total < TS::kCap ? total : TS::kCap;
   if (threadIdx.x == 0) {  // padding slot: no pair with it is ever inside the cutoff
-    t.x[kTileDummy] = 1e20;
-    t.y[kTileDummy] = 1e20;
-    t.z[kTileDummy] = 1e20;
+    t.x[TS::kDummy] = 1e20;
+    t.y[TS::kDummy] = 1e20;
+    t.z[TS::kDummy] = 1e20;
   }
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
     int lo = 0, hi = ntc;  // prefix[lo] <= u < prefix[hi]
@@ -134,23 +161,6 @@ __device__ __forceinline__ int tile_cell_of(const TS& t, int ntc, int u) {
     else hi = mid;
   } while (hi - lo > 1);
   return lo;
-}
-
-// slot[u] = sorted slot of tile particle u (u < min(total, kTileCap)).
-// Ends with a barrier.
-__device__ inline void tile_slots(const Grid& g, int total, const TileShared& t, int* slot) {
-  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
-  const int nt = total < kTileCap ? total : kTileCap;
-  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
-    int lo = 0, hi = ntc;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (t.prefix[mid] <= u) lo = mid;
-      else hi = mid;
-    }
-    slot[u] = t.src[lo] + (u - t.prefix[lo]);
-  }
-  __syncthreads();
 }
 
 // Tile cell of a brick particle from its cell key.

@@ -49,6 +49,7 @@ class mdpl_lj_params(ctypes.Structure):
         ("shift", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("max_nb", ctypes.c_int32),
+        ("newton", ctypes.c_int32),
     ]
 
 
@@ -135,7 +136,7 @@ def _stream(stream=None) -> int:
 
 
 def make_params(n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001, reuse_every=10,
-                shift="none", precision="fp32", max_nb=128) -> mdpl_lj_params:
+                shift="none", precision="fp32", max_nb=128, newton=False) -> mdpl_lj_params:
     p = mdpl_lj_params()
     p.n = int(n)
     for k in range(3):
@@ -145,6 +146,7 @@ def make_params(n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001
     p.shift = SHIFTS[shift] if isinstance(shift, str) else int(shift)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.max_nb = int(max_nb)
+    p.newton = int(bool(newton))
     return p
 
 

@@ -70,6 +70,16 @@ def test_workspace_bytes_validation(lib, kw, status):
     assert not h.value
 
 
+def test_newton_flag_validated(lib):
+    out = ctypes.c_size_t(0)
+    for v, status in ((0, C.MDPL_OK), (1, C.MDPL_OK), (2, C.MDPL_EINVAL), (-1, C.MDPL_EINVAL)):
+        p = _params()
+        p.newton = v
+        assert lib.mdpl_workspace_bytes(ctypes.byref(p), ctypes.byref(out)) == status
+    # the half-list context needs no more workspace than the full-list one
+    assert C.mdpl_workspace_bytes(_params(newton=True)) == C.mdpl_workspace_bytes(_params())
+
+
 def test_workspace_bytes_size(lib):
     p = _params(max_nb=128)
     b = C.mdpl_workspace_bytes(p)
