@@ -248,10 +248,11 @@ def main():
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
     ap.add_argument("--mlp-steps", type=int, default=6000)
-    ap.add_argument("--newton", action="store_true",
-                    help="time the run with half lists (each pair once, reactions by atomics)")
-    ap.add_argument("--no-newton-compare", action="store_true",
-                    help="skip the short half-list run reported beside the main one")
+    ap.add_argument("--pairs", choices=["full", "half", "cells"], default="full",
+                    help="pair loop of the timed run: full lists, half lists (Newton's third law) "
+                         "or no list (the cell stencil every pass)")
+    ap.add_argument("--no-pairs-compare", action="store_true",
+                    help="skip the short runs of the other pair loops reported beside the main one")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one elementwise copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -281,12 +282,12 @@ def main():
     n = d["pos"].shape[0]
     box = d["box"]
     log(f"N={n} box={box[0]:.4f} building context")
-    def timed_run(newton, warmup, steps):
+    def timed_run(pairs, warmup, steps):
         sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp32", shift="cutoff",
-                    max_nb=128, newton=newton)
+                    max_nb=128, pairs=pairs)
         state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
         torch.cuda.synchronize()
-        log(f"{'half' if newton else 'full'} lists: warmup {warmup} steps")
+        log(f"pairs={pairs}: warmup {warmup} steps")
         sim.run(state, warmup, 10)
         torch.cuda.synchronize()
         st, flags, _ = sim.check(raise_on_error=False)
@@ -307,22 +308,26 @@ def main():
         f_ms, f_n = C.mdpl_kernel_time(sim.handle, 0)
         fe_ms, fe_n = C.mdpl_kernel_time(sim.handle, 1)
         C.mdpl_set_timing(sim.handle, False)
-        entries = C.mdpl_nlist_entries(sim.handle)
+        entries = C.mdpl_nlist_entries(sim.handle) if pairs != "cells" else 0
         log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
             f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}")
         return dict(elapsed=elapsed, thermo=thermo.cpu().numpy(), f_ms=f_ms, f_n=f_n, fe_ms=fe_ms, fe_n=fe_n,
                     entries=entries)
 
-    r = timed_run(args.newton, args.warmup, args.steps)
+    r = timed_run(args.pairs, args.warmup, args.steps)
     elapsed, th, entries = r["elapsed"], r["thermo"], r["entries"]
     f_ms, f_n, fe_ms, fe_n = r["f_ms"], r["f_n"], r["fe_ms"], r["fe_n"]
     etot = th[:, 0] + th[:, 1]
 
-    if args.newton:
+    if args.pairs == "half":
         # the half-list force pass (timed with the clearing of the outputs): per
         # atom cnt (4) + own position (24, also the neighbour positions) + its
         # force (12, added by atomics); per list entry its 16-bit tile offset (2)
         alg_bytes = n * (4 + 24 + 12) + 2 * entries
+    elif args.pairs == "cells":
+        # the list-free pass: per atom its position (24, also the neighbour
+        # positions) and its force (12)
+        alg_bytes = n * (24 + 12)
     else:
         # algorithmic bytes of one plain force launch, which in the run also
         # applies the velocity-Verlet kick-kick-drift of the next step: per atom
@@ -332,7 +337,7 @@ def main():
         alg_bytes = n * (4 + 24 + 48 + 24) + 2 * entries
     avg_s = (f_ms / 1e3) / max(f_n, 1)
     achieved = alg_bytes / avg_s / 1e9
-    traffic = None if args.newton else measured_traffic()
+    traffic = measured_traffic() if args.pairs == "full" else None
 
     out = {
         "metric": METRIC,
@@ -351,8 +356,9 @@ def main():
             "workload": f"LJ fluid N={n} ({n_side}^3 sc lattice, rho 0.8442, T*=1, seed 2), rc 2.5, "
                         "skin 0.3, rebuild every 10 steps, dt 0.001, FP32 pair forces, FP64 "
                         "positions/energy/virial, PE+virial every 10 steps",
-            "neighbour_lists": "half (each pair once, reactions by atomics)" if args.newton
-                               else "full (every ordered pair)",
+            "neighbour_lists": {"full": "full (every ordered pair)",
+                                "half": "half (each pair once, reactions by atomics)",
+                                "cells": "none (each pass scans the 27-cell stencil)"}[args.pairs],
             "n_atoms": n,
             "nlist_entries_per_atom": entries / n,
             "precision": "FP32 pair force factor, forces stored as FP32; FP64 positions, velocities, "
@@ -360,8 +366,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_lj_force_half<float,float,false,false> (with the clearing of the forces)"
-                       if args.newton else "k_lj_force<float,float,false> (with the fused kick-kick-drift)"),
+            "kernel": {"full": "k_lj_force<float,float,false> (with the fused kick-kick-drift)",
+                       "half": "k_lj_force_half<float,float,false,false> (with the clearing of the forces)",
+                       "cells": "k_lj_force_cells<float,float,false>"}[args.pairs],
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -378,20 +385,25 @@ def main():
         "energy_drift_per_atom": float(np.max(np.abs(etot - etot[0])) / n),
         "hbm_gbs_force": achieved,
     }
-    if not args.newton and not args.no_newton_compare:
-        # the same workload with half lists (Newton's third law), a shorter run
-        h = timed_run(True, min(args.warmup, 20), min(args.steps, 200))
+    if args.pairs == "full" and not args.no_pairs_compare:
+        # the same workload with the other pair loops, shorter runs
         hs = min(args.steps, 200)
-        out["half_lists"] = {
-            "value": n * hs / h["elapsed"],
-            "unit": "atom-steps/s",
-            "steps": hs,
-            "ms_per_step": h["elapsed"] / hs * 1e3,
-            "force_us": h["f_ms"] / max(h["f_n"], 1) * 1e3,
-            "force_energy_virial_us": h["fe_ms"] / max(h["fe_n"], 1) * 1e3,
-            "nlist_entries_per_atom": h["entries"] / n,
-            "note": "force pass timed with the clearing of the outputs; the kicks run as their own pass",
-        }
+        for pairs, key, note in (
+                ("half", "half_lists", "force pass timed with the clearing of the outputs; the kicks run "
+                                       "as their own pass"),
+                ("cells", "cell_pair_loop", "no neighbour list: each force pass scans the 27-cell stencil; "
+                                            "the kicks run as their own pass")):
+            h = timed_run(pairs, min(args.warmup, 20), hs)
+            out[key] = {
+                "value": n * hs / h["elapsed"],
+                "unit": "atom-steps/s",
+                "steps": hs,
+                "ms_per_step": h["elapsed"] / hs * 1e3,
+                "force_us": h["f_ms"] / max(h["f_n"], 1) * 1e3,
+                "force_energy_virial_us": h["fe_ms"] / max(h["fe_n"], 1) * 1e3,
+                "nlist_entries_per_atom": h["entries"] / n,
+                "note": note,
+            }
     if not args.no_mlp:
         out["mlp_vs_lj"] = mlp_report(args)
     if not args.no_analysis:

@@ -70,6 +70,25 @@ typedef int32_t mdpl_status;
 #define MDPL_FP64 0
 #define MDPL_FP32 1
 
+/* How the pair loop finds the pairs within rc.
+ * FULL:  a neighbour list of every ordered pair within rc+skin, rebuilt
+ *        every reuse_every steps (Sec. 3.1); the pass writes only to the
+ *        first particle of a pair (Sec. 2), so no atomics and bit-reproducible
+ *        forces.
+ * HALF:  each pair listed once and its reaction applied to the second
+ *        particle (Newton's third law; Sec. 2, the comment on it beside the
+ *        pair loop); reactions are summed with atomics, so the last bits of
+ *        the forces vary from run to run.
+ * CELLS: no neighbour list: every force pass scans the 27-cell stencil of
+ *        the cell list built every reuse_every steps (cells of side >=
+ *        rc+skin, Sec. 3.1); bit-reproducible like FULL.
+ * The learned-potential entry points need FULL (MDPL_EINVAL otherwise);
+ * mdpl_nlist_export and mdpl_nlist_entries need a list (MDPL_ESTATE with
+ * CELLS). */
+#define MDPL_PAIRS_FULL 0
+#define MDPL_PAIRS_HALF 1
+#define MDPL_PAIRS_CELLS 2
+
 typedef struct {
   int64_t n;          /* number of particles, 1 .. 2^26 */
   double box[3];      /* periodic box [0,Lx) x [0,Ly) x [0,Lz) */
@@ -82,12 +101,7 @@ typedef struct {
   int32_t shift;      /* MDPL_SHIFT_* */
   int32_t precision;  /* MDPL_FP64 or MDPL_FP32 */
   int32_t max_nb;     /* neighbour-list capacity per particle (1 .. 1024) */
-  int32_t newton;     /* 0: full lists, every ordered pair (the pair loop of Sec. 2 over all
-                         j != i); 1: half lists, each pair once with the reaction -f_ij
-                         applied to j (Newton's third law; Sec. 2, the comment on it beside
-                         the pair loop): forces are summed with atomics, so their last
-                         bits vary from run to run, and the learned-potential entry points
-                         reject such a sim (MDPL_EINVAL) */
+  int32_t pairs;      /* MDPL_PAIRS_*: how the pair loop finds the pairs within rc */
 } mdpl_lj_params;
 
 typedef struct mdpl_sim mdpl_sim;
@@ -114,7 +128,8 @@ mdpl_status mdpl_sim_destroy(mdpl_sim* sim);
 
 /* Cell binning and neighbour-list construction for the given positions
  * (Sec. 3.1: cells of side >= rc+skin, 27-cell stencil, list of every j != i
- * with |r_i - r_j| < rc+skin under the minimum image).  Positions are first
+ * with |r_i - r_j| < rc+skin under the minimum image; with MDPL_PAIRS_HALF
+ * each pair once, with MDPL_PAIRS_CELLS the binning only).  Positions are first
  * folded into the box, x - L floor(x / L) (then x - L if that rounds to L),
  * and the list is that of the folded positions, tested exactly as
  * (dx*dx + dy*dy) + dz*dz < (rc+skin)^2 in double with the conditional
@@ -123,8 +138,8 @@ mdpl_status mdpl_sim_destroy(mdpl_sim* sim);
 mdpl_status mdpl_build(mdpl_sim* sim, const double* x, const double* y, const double* z);
 
 /* Copy the list of the last mdpl_build as directed pairs (i, j) in the
- * caller's particle indices, unordered (with newton = 1 each pair appears
- * once, in one direction).  Writes min(count, cap) pairs,
+ * caller's particle indices, unordered (with MDPL_PAIRS_HALF each pair
+ * appears once, in one direction).  Writes min(count, cap) pairs,
  * returns the total in *count_host.  Synchronises the stream. */
 mdpl_status mdpl_nlist_export(mdpl_sim* sim, int32_t* i_out, int32_t* j_out, int64_t cap,
                               int64_t* count_host);

@@ -101,7 +101,8 @@ mdpl_status validate(const mdpl_lj_params* p) {
   if (p->shift < 0 || p->shift > 2) return MDPL_EINVAL;
   if (p->precision != MDPL_FP64 && p->precision != MDPL_FP32) return MDPL_EINVAL;
   if (p->max_nb < 1 || p->max_nb > 1024) return MDPL_EINVAL;
-  if (p->newton != 0 && p->newton != 1) return MDPL_EINVAL;
+  if (p->pairs != MDPL_PAIRS_FULL && p->pairs != MDPL_PAIRS_HALF && p->pairs != MDPL_PAIRS_CELLS)
+    return MDPL_EINVAL;
   Grid g;
   int unit[3] = {1, 1, 1};
   return make_grid(p->box, p->rc + p->skin, unit, &g);
@@ -118,9 +119,10 @@ void lj_grid(const mdpl_lj_params* p, Grid* g, int* threads) {
   const double per_cell = (double)p->n / ((double)g->nc[0] * g->nc[1] * g->nc[2]);
   int b = 1;
   for (int cand = 3; cand >= 1; --cand) {
-    const int w = cand + 2, cells = p->newton ? w * w * w - ((w + 1) * w + 1) : w * w * w;
+    const bool half = p->pairs == MDPL_PAIRS_HALF;
+    const int w = cand + 2, cells = half ? w * w * w - ((w + 1) * w + 1) : w * w * w;
     const double tile = cells * per_cell;
-    if (p->newton ? tile <= 0.9 * (kTileMaxHalf - 1) : tile <= 0.85 * kTileMax) {
+    if (half ? tile <= 0.9 * (kTileMaxHalf - 1) : tile <= 0.85 * kTileMax) {
       b = cand;
       break;
     }
@@ -289,7 +291,8 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->tl.cnt = take<int32_t>(w, 4 * (size_t)s->npad);
   s->tl.stride = s->npad;
   s->tl.max_nb = p->max_nb;
-  s->tl.half = p->newton;
+  s->tl.half = p->pairs == MDPL_PAIRS_HALF;
+  s->tl.cells = p->pairs == MDPL_PAIRS_CELLS;
   s->tl.threads = threads;
   s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
   s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
@@ -327,17 +330,18 @@ mdpl_status mdpl_build(mdpl_sim* s, const double* x, const double* y, const doub
   HIP_TRY(hipMemcpyAsync(s->perm, svals, 4 * (size_t)s->n, hipMemcpyDeviceToDevice, s->st));
   s->skeys = skeys;
   HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, true, s->st));
-  HIP_TRY(build_tile_nlist(s->sx, s->sy, s->sz, skeys, s->cell_start, s->g, s->r2ext, s->tl,
-                           s->flags, s->maxcount, s->st));
+  if (!s->tl.cells)
+    HIP_TRY(build_tile_nlist(s->sx, s->sy, s->sz, skeys, s->cell_start, s->g, s->r2ext, s->tl,
+                             s->flags, s->maxcount, s->st));
   s->built = true;
-  s->have_list = true;
+  s->have_list = !s->tl.cells;
   return MDPL_OK;
 }
 
 mdpl_status mdpl_nlist_export(mdpl_sim* s, int32_t* i_out, int32_t* j_out, int64_t cap,
                               int64_t* count_host) {
   if (!s || !count_host || cap < 0 || (cap > 0 && (!i_out || !j_out))) return MDPL_EINVAL;
-  if (!s->built) return MDPL_ESTATE;
+  if (!s->built || s->tl.cells) return MDPL_ESTATE;
   HIP_TRY(exclusive_scan(s->tl.cnt, s->offsets, s->n, s->sort.blocksums, true, s->st));
   if (cap > 0)
     HIP_TRY(export_tile_pairs(s->tl, s->cell_start, s->g, s->perm, s->offsets, i_out, j_out, cap,
@@ -385,6 +389,7 @@ mdpl_status mdpl_lj_backward(mdpl_sim* s, const double* x, const double* y, cons
   out.scale = -1.0;
   out.scale_dev = grad_e;
   out.fuse = false;
+  out.flags = s->flags;
   // FP64 arithmetic for the FP64 context, FP32 pair math for the FP32 one;
   // the gradient is stored in double either way
   const int kind = s->p.precision == MDPL_FP64 ? 2 : 3;
@@ -473,10 +478,11 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     StateArrays t = cur;
     cur = other;
     other = t;
-    HIP_TRY(build_tile_nlist(cur.x, cur.y, cur.z, skeys, s->cell_start, s->g, s->r2ext, s->tl,
-                             s->flags, s->maxcount, s->st));
+    if (!s->tl.cells)
+      HIP_TRY(build_tile_nlist(cur.x, cur.y, cur.z, skeys, s->cell_start, s->g, s->r2ext, s->tl,
+                               s->flags, s->maxcount, s->st));
     have_ref = true;
-    s->have_list = true;
+    s->have_list = !s->tl.cells;
     return MDPL_OK;
   };
   auto row = [&](int64_t step) { return thermo + 4 * (step / sample_every); };
@@ -568,8 +574,9 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
   const int prec = s->p.precision;
   StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
-  // with half lists a force is complete only when its pass has ended: no fused kicks
-  return run_loop(s, user, nsteps, sample_every, thermo, !s->tl.half,
+  // the kicks are fused into the full-list pass only (a half-list force is
+  // complete only when its pass has ended; the cell pass has no fused form)
+  return run_loop(s, user, nsteps, sample_every, thermo, !s->tl.half && !s->tl.cells,
                   [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool fuse,
                       double* const* spare, double* ke) {
                     return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr,
@@ -680,7 +687,7 @@ mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t 
 // ------------------------------------------------------- learned potential
 mdpl_status mdpl_desc_fwd(mdpl_sim* s, const double* x, const double* y, const double* z, float* G,
                           float* mom) {
-  if (!s || !x || !y || !z || !G || s->tl.half) return MDPL_EINVAL;
+  if (!s || !x || !y || !z || !G || s->tl.half || s->tl.cells) return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
   HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   HIP_TRY(desc_forward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm, G,
@@ -691,7 +698,8 @@ mdpl_status mdpl_desc_fwd(mdpl_sim* s, const double* x, const double* y, const d
 mdpl_status mdpl_desc_bwd(mdpl_sim* s, const double* x, const double* y, const double* z,
                           const float* dEdG, const float* mom, float* fx, float* fy,
                           float* fz) {
-  if (!s || !x || !y || !z || !dEdG || !mom || !fx || !fy || !fz || s->tl.half) return MDPL_EINVAL;
+  if (!s || !x || !y || !z || !dEdG || !mom || !fx || !fy || !fz || s->tl.half || s->tl.cells)
+    return MDPL_EINVAL;
   if (!s->built) return MDPL_ESTATE;
   HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, s->n, s->g, s->sx, s->sy, s->sz, s->st));
   HIP_TRY(desc_backward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm,
@@ -781,7 +789,7 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
   if (!s || !mlp_ok(w) || !ws || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids)
     return MDPL_EINVAL;
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
-  if (s->p.precision != MDPL_FP32 || s->tl.half) return MDPL_EINVAL;
+  if (s->p.precision != MDPL_FP32 || s->tl.half || s->tl.cells) return MDPL_EINVAL;
   const int64_t n = s->n;
   if (ws_floats < (int64_t)kMlpRunFloats * n) return MDPL_EWORKSPACE;
   float* G = ws;

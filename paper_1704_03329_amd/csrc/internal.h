@@ -127,6 +127,7 @@ struct TileList {
   int max_nb;       // multiple of 4
   int threads;      // workgroup size of the tile kernels
   int half;         // 1: each pair once (Newton's third law), tiles of kTileMaxHalf slots
+  int cells;        // 1: no list; the pair loop scans the cell stencil (nbr and cnt unused)
 };
 hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
                             const int32_t* skeys, const int32_t* cell_start, const Grid& g,
@@ -155,7 +156,7 @@ struct ForceOut {
   double *vx, *vy, *vz;   // velocities, updated in place
   double *nx, *ny, *nz;   // new positions (a different buffer from x, y, z)
   double h, dt;
-  uint32_t* flags;        // MDPL_FLAG_NONFINITE on a non-finite velocity
+  uint32_t* flags;        // MDPL_FLAG_NONFINITE on a non-finite velocity; tile overflow (no list)
 };
 // Partials are written per brick (nblocks_out = number of bricks).
 hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,

@@ -388,6 +388,139 @@ void k_lj_force_half(const double* __restrict__ x, const double* __restrict__ y,
   }
 }
 
+// ------------------------------------------------------------ no list
+// The pair loop straight from the cell list (Sec. 3.1 without the neighbour
+// list): one wave per home cell of the brick; its na particles are spread
+// over the 64 lanes as na x K (K = 64 / na) and lane (a, k) visits
+// candidates k, k+K, ... of each of the 9 stencil rows (three consecutive
+// tile cells, one contiguous range of the tile of FP64 image positions).
+// Separations, the cutoff test and the pair force are those of k_lj_force;
+// each lane sums its candidates in FP64 and the K partial sums of a
+// particle are added in a fixed order with cross-lane reads, so the result
+// is reproducible.  A tile over its capacity raises the overflow flag.
+template <typename MT, typename OT, bool ENERGY>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+void k_lj_force_cells(const double* __restrict__ x, const double* __restrict__ y,
+                      const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g,
+                      LJConst c, ForceOut out) {
+  __shared__ TileShared t;
+  __shared__ double red[32];  // up to 16 waves: e, w
+  const int brick = brick_of_block(g.nbricks);
+  if (brick >= g.nbricks) return;
+  const int total = tile_cells(g, brick, cs, t);
+  if (threadIdx.x == 0 && total > kTileCap) atomicOr(out.flags, MDPL_FLAG_NL_OVERFLOW);
+  tile_load<true>(g, x, y, z, total, t);  // ends with a barrier
+  const double sig6 = c.sigma2 * c.sigma2 * c.sigma2;
+  const MT fa = (MT)(48.0 * c.eps * sig6 * sig6), fb = (MT)(24.0 * c.eps * sig6);
+  double scale = out.scale;
+  if (out.scale_dev) scale *= *out.scale_dev;
+  const int TX = g.B[0] + 2, TXY = TX * (g.B[1] + 2);
+  int bx, by, bz;
+  brick_coords(g, brick, bx, by, bz);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  double e = 0.0, w = 0.0;
+  for (int lc = wave; lc < g.V; lc += nwaves) {
+    const int lx = lc % g.B[0], ly = (lc / g.B[0]) % g.B[1], lz = lc / (g.B[0] * g.B[1]);
+    // the last brick along an axis may be partial: its missing cells would
+    // alias periodic images of another brick's cells
+    if (bx * g.B[0] + lx >= g.nc[0] || by * g.B[1] + ly >= g.nc[1] || bz * g.B[2] + lz >= g.nc[2])
+      continue;
+    const int tc0 = ((lz + 1) * (g.B[1] + 2) + (ly + 1)) * TX + (lx + 1);
+    const int ncell = t.prefix[tc0 + 1] - t.prefix[tc0];
+    for (int a0 = 0; a0 < ncell; a0 += 64) {
+      const int na = ncell - a0 < 64 ? ncell - a0 : 64;
+      const int K = 64 / na;
+      const int a = a0 + lane % na, k = lane / na;
+      const int self = t.prefix[tc0] + a;
+      const bool ok = k < K && self < kTileCap;
+      const double xi = ok ? t.x[self] : 0.0, yi = ok ? t.y[self] : 0.0, zi = ok ? t.z[self] : 0.0;
+      double ax = 0.0, ay = 0.0, az = 0.0, ei = 0.0;
+      for (int oz = -1; oz <= 1; ++oz) {
+        for (int oy = -1; oy <= 1; ++oy) {
+          const int tcl = tc0 + oz * TXY + oy * TX - 1;
+          int ue = t.prefix[tcl + 3];
+          ue = ue < kTileCap ? ue : kTileCap;
+          if (!ok) ue = 0;
+#pragma unroll 4
+          for (int u = t.prefix[tcl] + k; u < ue; u += K) {
+            const double dx = xi - t.x[u], dy = yi - t.y[u], dz = zi - t.z[u];
+            double gd;
+            if (ENERGY) {
+              const double d2 = sq_sum(dx, dy, dz);
+              const bool in = d2 < c.rc2 && u != self;
+              double inv = __builtin_amdgcn_rcp(d2);
+              inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
+              inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
+              const double s2 = c.sigma2 * inv;
+              const double s6 = s2 * s2 * s2;
+              const double gg = 48.0 * c.eps * inv * s6 * (s6 - 0.5);
+              const double v = 4.0 * c.eps * (s6 * s6 - s6) + c.shift_v;
+              gd = in ? gg : 0.0;
+              ei += in ? 0.5 * v : 0.0;
+              w += 0.5 * gd * d2;
+            } else {
+              const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+              const bool in = d2 < c.rc2 && u != self;
+              MT inv;
+              if constexpr (sizeof(MT) == 4) {
+                inv = __builtin_amdgcn_rcpf(in ? (float)d2 : 3.0e38f);
+              } else {
+                inv = 1.0 / d2;
+              }
+              const MT x2 = inv * inv;
+              MT gg = (x2 * x2) * (fa * (x2 * inv) - fb);
+              if constexpr (sizeof(MT) != 4) gg = in ? gg : (MT)0;
+              gd = (double)gg;
+            }
+            ax = __builtin_fma(gd, dx, ax);
+            ay = __builtin_fma(gd, dy, ay);
+            az = __builtin_fma(gd, dz, az);
+          }
+        }
+      }
+      // the K partial sums of particle a, in the order k = 0, 1, ..., K - 1
+      const int base = lane % na;
+      double sx = ax, sy = ay, sz = az, se = ei;
+      for (int kk = 1; kk < K; ++kk) {
+        const int src = base + na * kk;
+        sx += __shfl(ax, src, 64);
+        sy += __shfl(ay, src, 64);
+        sz += __shfl(az, src, 64);
+        if (ENERGY) se += __shfl(ei, src, 64);
+      }
+      if (!ok || k != 0) continue;
+      const int s = t.src[tc0] + a;
+      const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
+      ((OT*)out.fx)[o] = (OT)(sx * scale);
+      ((OT*)out.fy)[o] = (OT)(sy * scale);
+      ((OT*)out.fz)[o] = (OT)(sz * scale);
+      if (ENERGY) {
+        if (out.e_atom) out.e_atom[o] = se;
+        e += se;
+      }
+    }
+  }
+  if (ENERGY) {
+    e = wave_sum(e);
+    w = wave_sum(w);
+    if (lane == 0) {
+      red[wave] = e;
+      red[16 + wave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double pe = 0.0, ww = 0.0;
+      for (int q = 0; q < nwaves; ++q) {
+        pe += red[q];
+        ww += red[16 + q];
+      }
+      out.partials[2 * brick] = pe;
+      out.partials[2 * brick + 1] = ww;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill0(T* __restrict__ a, T* __restrict__ b,
                                                T* __restrict__ c, int64_t n) {
@@ -405,6 +538,16 @@ static void launch_force(bool energy, hipStream_t st, const double* x, const dou
                          const LJConst& c, const ForceOut& out, int64_t n) {
   const dim3 grid(tile_grid_blocks(g.nbricks));
   const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
+  if (tl.cells) {
+    const unsigned waves = g.V * 64 < 1024 ? (unsigned)g.V * 64 : 1024u;  // one wave per home cell
+    if (energy)
+      hipLaunchKernelGGL((k_lj_force_cells<MT, OT, true>), grid, dim3(waves), 0, st, x, y, z, cs, g,
+                         c, out);
+    else
+      hipLaunchKernelGGL((k_lj_force_cells<MT, OT, false>), grid, dim3(waves), 0, st, x, y, z, cs, g,
+                         c, out);
+    return;
+  }
   if (tl.half) {
     // outputs accumulate with atomics: clear them first (caller order, n entries)
     const dim3 zb((unsigned)div_up(n, 256));

@@ -23,6 +23,7 @@ MDPL_ENONFINITE, MDPL_EHIP, MDPL_ESTATE, MDPL_EWORKSPACE = 5, 6, 7, 8
 FLAG_NL_OVERFLOW, FLAG_SKIN, FLAG_NONFINITE = 1, 2, 4
 SHIFTS = {"none": 0, "paper": 1, "cutoff": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
+PAIRS = {"full": 0, "half": 1, "cells": 2}
 
 
 class MdplError(RuntimeError):
@@ -49,7 +50,7 @@ class mdpl_lj_params(ctypes.Structure):
         ("shift", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("max_nb", ctypes.c_int32),
-        ("newton", ctypes.c_int32),
+        ("pairs", ctypes.c_int32),
     ]
 
 
@@ -136,7 +137,7 @@ def _stream(stream=None) -> int:
 
 
 def make_params(n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001, reuse_every=10,
-                shift="none", precision="fp32", max_nb=128, newton=False) -> mdpl_lj_params:
+                shift="none", precision="fp32", max_nb=128, pairs="full") -> mdpl_lj_params:
     p = mdpl_lj_params()
     p.n = int(n)
     for k in range(3):
@@ -146,7 +147,7 @@ def make_params(n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001
     p.shift = SHIFTS[shift] if isinstance(shift, str) else int(shift)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.max_nb = int(max_nb)
-    p.newton = int(bool(newton))
+    p.pairs = PAIRS[pairs] if isinstance(pairs, str) else int(pairs)
     return p
 
 

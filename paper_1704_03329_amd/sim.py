@@ -20,9 +20,9 @@ class LJSim:
     """A Lennard-Jones simulation context (mdpl_sim) with its workspace."""
 
     def __init__(self, n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001, reuse_every=10,
-                 shift="none", precision="fp32", max_nb=128, newton=False, device="cuda", stream=None):
+                 shift="none", precision="fp32", max_nb=128, pairs="full", device="cuda", stream=None):
         self.params = C.make_params(n, box, rc, skin, eps, sigma, mass, dt, reuse_every, shift, precision,
-                                    max_nb, newton)
+                                    max_nb, pairs)
         self.n = int(n)
         self.box = [float(b) for b in box]
         self.device = torch.device(device)

@@ -70,14 +70,16 @@ def test_workspace_bytes_validation(lib, kw, status):
     assert not h.value
 
 
-def test_newton_flag_validated(lib):
+def test_pairs_mode_validated(lib):
     out = ctypes.c_size_t(0)
-    for v, status in ((0, C.MDPL_OK), (1, C.MDPL_OK), (2, C.MDPL_EINVAL), (-1, C.MDPL_EINVAL)):
+    for v, status in ((0, C.MDPL_OK), (1, C.MDPL_OK), (2, C.MDPL_OK), (3, C.MDPL_EINVAL), (-1, C.MDPL_EINVAL)):
         p = _params()
-        p.newton = v
+        p.pairs = v
         assert lib.mdpl_workspace_bytes(ctypes.byref(p), ctypes.byref(out)) == status
-    # the half-list context needs no more workspace than the full-list one
-    assert C.mdpl_workspace_bytes(_params(newton=True)) == C.mdpl_workspace_bytes(_params())
+    # the other pair modes need no more workspace than full lists
+    full = C.mdpl_workspace_bytes(_params())
+    assert C.mdpl_workspace_bytes(_params(pairs="half")) == full
+    assert C.mdpl_workspace_bytes(_params(pairs="cells")) == full
 
 
 def test_workspace_bytes_size(lib):

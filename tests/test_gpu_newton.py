@@ -24,7 +24,7 @@ def _sim(n, box, **kw):
     from paper_1704_03329_amd.sim import LJSim
 
     gpu_device()
-    return LJSim(n, box, newton=True, **kw)
+    return LJSim(n, box, pairs="half", **kw)
 
 
 def _undirected(p, n):
