@@ -49,6 +49,12 @@ __device__ __forceinline__ double exact_sep(double xi, double yi, double zi, dou
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// (dx*dx + dy*dy) + dz*dz with each operation rounded (no contraction)
+__device__ __forceinline__ double sq_sum(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

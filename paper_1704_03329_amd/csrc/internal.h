@@ -162,6 +162,15 @@ struct ForceOut {
 hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,
                     const Grid& g, const TileList& tl, const LJConst& c, int precision, bool energy,
                     const ForceOut& out, int64_t n, hipStream_t st, int* nblocks_out);
+// the same with half lists (outputs cleared, then summed with atomics) and
+// with no list (the cell stencil)
+hipError_t lj_force_half(const double* x, const double* y, const double* z,
+                         const int32_t* cell_start, const Grid& g, const TileList& tl,
+                         const LJConst& c, int precision, bool energy, const ForceOut& out,
+                         int64_t n, hipStream_t st);
+hipError_t lj_force_cells(const double* x, const double* y, const double* z,
+                          const int32_t* cell_start, const Grid& g, const LJConst& c,
+                          int precision, bool energy, const ForceOut& out, hipStream_t st);
 
 // Velocity Verlet particle loops on the sorted state (INC on v and r).
 //   mode 0: v += h F ; r += dt v                          (first step)
