@@ -5,7 +5,7 @@
  * The operations follow the problem statement of Saunders, Grant & Mueller,
  * "A Domain Specific Language for Performance Portable Molecular Dynamics
  * Algorithms" (arXiv:1704.03329): N particles with positions, velocities
- * and mass in a periodic box (Sec. 3.1), a cutoff r_c and an extra shell
+ * and mass in a periodic box (Sec. 3.5), a cutoff r_c and an extra shell
  * delta for neighbour-list reuse (Eq. extended_cutoff), the Lennard-Jones
  * pair loop (Eqs. LJpotential, LJforce), the velocity-Verlet particle loops
  * (Alg. VelocityVerlet), the bond-order analysis (Sec. 4.1) and the
@@ -72,7 +72,7 @@ typedef int32_t mdpl_status;
 
 /* How the pair loop finds the pairs within rc.
  * FULL:  a neighbour list of every ordered pair within rc+skin, rebuilt
- *        every reuse_every steps (Sec. 3.1); the pass writes only to the
+ *        every reuse_every steps (Sec. 3.5); the pass writes only to the
  *        first particle of a pair (Sec. 2), so no atomics and bit-reproducible
  *        forces.
  * HALF:  each pair listed once and its reaction applied to the second
@@ -81,7 +81,7 @@ typedef int32_t mdpl_status;
  *        the forces vary from run to run.
  * CELLS: no neighbour list: every force pass scans the 27-cell stencil of
  *        the cell list built every reuse_every steps (cells of side >=
- *        rc+skin, Sec. 3.1); bit-reproducible like FULL.
+ *        rc+skin, Sec. 3.5); bit-reproducible like FULL.
  * The learned-potential entry points need FULL (MDPL_EINVAL otherwise);
  * mdpl_nlist_export and mdpl_nlist_entries need a list (MDPL_ESTATE with
  * CELLS). */
@@ -127,7 +127,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t wor
 mdpl_status mdpl_sim_destroy(mdpl_sim* sim);
 
 /* Cell binning and neighbour-list construction for the given positions
- * (Sec. 3.1: cells of side >= rc+skin, 27-cell stencil, list of every j != i
+ * (Sec. 3.5: cells of side >= rc+skin, 27-cell stencil, list of every j != i
  * with |r_i - r_j| < rc+skin under the minimum image; with MDPL_PAIRS_HALF
  * each pair once, with MDPL_PAIRS_CELLS the binning only).  Positions are first
  * folded into the box, x - L floor(x / L) (then x - L if that rounds to L),
@@ -299,7 +299,7 @@ mdpl_status mdpl_scale_velocities(double* vx, double* vy, double* vz, int64_t n,
 mdpl_status mdpl_mlp_run_floats(int64_t n, int64_t* floats_host);
 
 /* mdpl_run with the learned potential as the force field (Alg.
- * VelocityVerlet with list reuse, Sec. 3.1; forces F = -grad sum_i E_i).
+ * VelocityVerlet with list reuse, Sec. 3.5; forces F = -grad sum_i E_i).
  * Same state arrays, in-place reordering, ids, flags and rebuild rule as
  * mdpl_run; the sim must have precision MDPL_FP32 (forces are float) and
  * its rc is the descriptor cutoff.  thermo rows: KE, sum_i E_i (FP64 sum

@@ -12,6 +12,8 @@ numpy / scipy FP64, slow and obviously correct:
   velocity-Verlet loop (Alg. VelocityVerlet).
 * ``oracle.boa``   Steinhardt bond-order parameters (Eqs. Qell, qellm;
   Algs. sph_I / sph_II), spherical harmonics from scipy.
+* ``oracle.thermostat``  the Andersen thermostat of the crystallisation run
+  (Sec. 5.2) with Philox4x64-10 random numbers (readings in its header).
 * ``oracle.cna``   common-neighbour analysis with literal Python sets
   (Eqs. Ei, Ei_ordered, Algs. cna_I/II/III, Alg. max_cluster_size).
 * ``oracle.descriptor`` / ``oracle.mlp``  the descriptor-MLP potential

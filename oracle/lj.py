@@ -3,9 +3,9 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Everything here is the plain all-pairs definition (the sequential pair loop
-over all ordered pairs i != j of Sec. 3, Listing "simplest_pairloop"),
+over all ordered pairs i != j of Sec. 3.4, Listing "simplest_pairloop"),
 evaluated with the minimum-image convention in a periodic orthorhombic box
-[0,Lx) x [0,Ly) x [0,Lz) (Sec. 3.1).  Cell and neighbour lists only reach
+[0,Lx) x [0,Ly) x [0,Lz) (Sec. 3.5).  Cell and neighbour lists only reach
 this result faster, so the oracle never builds them.
 
 Exact operation order (shared contract with any implementation that claims
@@ -35,6 +35,8 @@ from __future__ import annotations
 import math
 
 import numpy as np
+
+from . import thermostat
 
 SHIFT_MODES = ("none", "paper", "cutoff")
 
@@ -175,11 +177,15 @@ def wrap(pos, box):
 
 
 def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float = 1.0, sigma: float = 1.0,
-                    mass: float = 1.0, shift: str = "none", sample_every: int = 0, force_fn=None):
+                    mass: float = 1.0, shift: str = "none", sample_every: int = 0, force_fn=None,
+                    andersen=None):
     """Velocity Verlet exactly in the order of Alg. VelocityVerlet.
 
     force_fn(x) -> dict(F, pe, w) replaces the LJ force field when given
-    (the algorithm is the same for any force field).
+    (the algorithm is the same for any force field).  andersen: optional
+    dict(temperature, nu, seed, step0, ids) adding the collisions of
+    oracle.thermostat after each step's second half kick (and after its
+    thermo sample); global step = step0 + local step, ids the particles' ids.
 
     F(r_0) is computed before the first step (the algorithm uses F in its
     first half kick without showing its computation).  Per step:
@@ -210,6 +216,9 @@ def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float
         v = v + h * F
         if sample_every and step % sample_every == 0:
             thermo.append((step, kinetic_energy(v, mass), res["pe"], res["w"]))
+        if andersen is not None:
+            v, _ = thermostat.andersen(v, andersen["ids"], andersen["step0"] + step, andersen["temperature"],
+                                       andersen["nu"], dt, andersen["seed"], mass)
     return {"pos": x, "vel": v, "F": F, "thermo": np.array(thermo, dtype=np.float64).reshape(-1, 4)}
 
 

@@ -446,7 +446,7 @@ mdpl_status mdpl_kernel_time(mdpl_sim* s, int32_t which, double* ms, int64_t* la
 
 namespace {
 
-// The time loop of Alg. VelocityVerlet with list reuse (Sec. 3.1), shared by
+// The time loop of Alg. VelocityVerlet with list reuse (Sec. 3.5), shared by
 // the LJ and learned-potential runs.  force(cur, energy, pe_w_dst, slot)
 // fills cur.f* from cur positions (and PE, W into pe_w_dst on sampled steps).
 template <typename ForceFn>

@@ -1,4 +1,4 @@
-// Cell binning by counting sort (Sec. 3.1: every particle belongs to exactly
+// Cell binning by counting sort (Sec. 3.5: every particle belongs to exactly
 // one cell of side >= the list radius; the GPU cell-occupancy idea of the
 // "Threading and GPU parallelisation" paragraph is realised here as a stable
 // LSD radix sort of cell keys).

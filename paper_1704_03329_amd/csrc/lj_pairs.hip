@@ -188,7 +188,7 @@ void k_lj_force_half(const double* __restrict__ x, const double* __restrict__ y,
 }
 
 // ------------------------------------------------------------ no list
-// The pair loop straight from the cell list (Sec. 3.1 without the neighbour
+// The pair loop straight from the cell list (Sec. 3.5 without the neighbour
 // list): one wave per home cell of the brick; its na particles are spread
 // over the 64 lanes as na x K (K = 64 / na) and lane (a, k) visits
 // candidates k, k+K, ... of each of the 9 stencil rows (three consecutive

@@ -1,4 +1,4 @@
-// Neighbour-list construction from the cell list (Sec. 3.1: visit the cell
+// Neighbour-list construction from the cell list (Sec. 3.5: visit the cell
 // of i and its 26 neighbours, keep the pairs closer than the list radius;
 // GPU neighbour matrix W_{m,i} = m-th neighbour of i).
 //

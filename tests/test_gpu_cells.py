@@ -1,5 +1,5 @@
 """GPU parity of the list-free LJ pair loop (every pass scans the 27-cell
-stencil of the cell list, Sec. 3.1, with no neighbour list) against the
+stencil of the cell list, Sec. 3.5, with no neighbour list) against the
 same FP64 oracle as the lists.
 
 Bars as for the full lists: ||dF||/||F|| <= 1e-5 and max_i |dF_i| <= 1e-5
