@@ -179,6 +179,28 @@ mdpl_status mdpl_run(mdpl_sim* sim, double* x, double* y, double* z, double* vx,
                      double* vz, void* fx, void* fy, void* fz, int32_t* ids, int64_t nsteps,
                      int32_t sample_every, double* thermo);
 
+/* mdpl_run with the Andersen thermostat of the crystallisation run (Sec.
+ * 5.2; the paper gives neither the collision rule nor the random numbers,
+ * so these are readings): after the kick that completes step g (after its
+ * thermo sample), each particle collides with probability p =
+ * collision_rate * dt (must be <= 1) and takes a velocity with components
+ * sqrt(temperature / mass) * N(0, 1).  The draws come from Philox4x64-10
+ * (Salmon et al., SC'11) with key (seed, 0) and counter (g, id, block, 0),
+ * id = the particle's value in `ids` at the call (its original id), so they
+ * do not depend on the in-place reordering: with block 0 = (b0..b3) and
+ * block 1 = (b4, ...), U(b) = (b >> 11) 2^-53, the particle collides iff
+ * U(b0) < p and then takes sqrt(-2 ln(1 - U(b1))) (cos, sin)(2 pi U(b2)) and
+ * sqrt(-2 ln(1 - U(b3))) cos(2 pi U(b4)).  Global steps are step0 + 1 ..
+ * step0 + nsteps, so a run continued with step0 += nsteps continues the
+ * streams.  temperature 0 stops the collided particles.  The kicks are not
+ * fused into the force pass.  Arguments otherwise as mdpl_run; MDPL_EINVAL
+ * for a negative temperature, rate or step0. */
+mdpl_status mdpl_run_andersen(mdpl_sim* sim, double* x, double* y, double* z, double* vx,
+                              double* vy, double* vz, void* fx, void* fy, void* fz, int32_t* ids,
+                              int64_t nsteps, int32_t sample_every, double* thermo,
+                              double temperature, double collision_rate, uint64_t seed,
+                              int64_t step0);
+
 /* Synchronise the stream and read the device flags (MDPL_FLAG_* bits) and
  * the largest neighbour count seen (so max_nb can be raised).  Returns
  * MDPL_ECAPACITY, MDPL_ESKIN or MDPL_ENONFINITE if the matching bit is set

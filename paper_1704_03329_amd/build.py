@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdpl.so")
 
-SOURCES = ["api.hip", "binning.hip", "nlist.hip", "lj.hip", "lj_pairs.hip", "analysis.hip", "desc.hip",
-           "mlp.hip"]
+SOURCES = ["api.hip", "binning.hip", "nlist.hip", "lj.hip", "lj_pairs.hip", "integrate.hip", "analysis.hip",
+           "desc.hip", "mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -449,9 +449,11 @@ namespace {
 // The time loop of Alg. VelocityVerlet with list reuse (Sec. 3.5), shared by
 // the LJ and learned-potential runs.  force(cur, energy, pe_w_dst, slot)
 // fills cur.f* from cur positions (and PE, W into pe_w_dst on sampled steps).
+// th (nullable): Andersen collisions after every completed step; global
+// step numbers start at th->step (the step0 of mdpl_run_andersen) + 1.
 template <typename ForceFn>
 mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t sample_every,
-                     double* thermo, bool can_fuse, ForceFn force) {
+                     double* thermo, bool can_fuse, ForceFn force, const Andersen* th = nullptr) {
   const int64_t n = s->n;
   const int prec = s->p.precision;
   const int ns = s->p.reuse_every;
@@ -462,6 +464,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
   StateArrays alt{s->sx, s->sy, s->sz, s->avx, s->avy, s->avz, s->afx, s->afy, s->afz, s->aids};
   StateArrays cur = user, other = alt;
   double* spare[3] = {s->px, s->py, s->pz};
+  Andersen thermo_cfg{};
   bool have_ref = false;
   s->built = false;  // the standalone build is overwritten
 
@@ -499,13 +502,22 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(0), ke_scale, s->st));
     HIP_TRY(hipMemcpyAsync(row(0) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
   }
+  // the collisions at the end of global step g (the kick completing it is in vv_step)
+  auto collide = [&](int64_t local) -> const Andersen* {
+    if (!th) return nullptr;
+    thermo_cfg = *th;
+    thermo_cfg.ids = cur.ids;
+    thermo_cfg.step = th->step + local;
+    return &thermo_cfg;
+  };
   bool fused = false;  // the last force pass already applied this step's kick-kick-drift
   for (int64_t step = 1; step <= nsteps; ++step) {
     if (!fused) {
       const bool ke = step > 1 && sampled(step - 1);
       int nb = 0;
       HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
-                      h, dt, step == 1 ? 0 : 1, ke, s->partials, s->flags, s->st, &nb));
+                      h, dt, step == 1 ? 0 : 1, ke, s->partials, s->flags, s->st, &nb,
+                      step == 1 ? nullptr : collide(step - 1)));
       if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(step - 1), ke_scale, s->st));
     }
     if (step % ns == 0) {
@@ -533,7 +545,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     const bool ke = sampled(nsteps);
     int nb = 0;
     HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
-                    h, dt, 2, ke, s->partials, s->flags, s->st, &nb));
+                    h, dt, 2, ke, s->partials, s->flags, s->st, &nb, collide(nsteps)));
     if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(nsteps), ke_scale, s->st));
   }
   // close the last reuse period
@@ -583,6 +595,29 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
                                         en, nullptr, pe_w, prec, slot, fuse ? &cur : nullptr,
                                         spare, ke);
                   });
+}
+
+mdpl_status mdpl_run_andersen(mdpl_sim* s, double* x, double* y, double* z, double* vx,
+                              double* vy, double* vz, void* fx, void* fy, void* fz, int32_t* ids,
+                              int64_t nsteps, int32_t sample_every, double* thermo,
+                              double temperature, double collision_rate, uint64_t seed,
+                              int64_t step0) {
+  if (!s || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids) return MDPL_EINVAL;
+  if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo) || step0 < 0) return MDPL_EINVAL;
+  const double p = collision_rate * s->p.dt;
+  if (!(temperature >= 0.0) || !isfinite(temperature) || !(collision_rate >= 0.0) || !(p <= 1.0))
+    return MDPL_EINVAL;
+  const int prec = s->p.precision;
+  const Andersen th{nullptr, p, sqrt(temperature / s->p.mass), seed, step0};
+  StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
+  // the collisions sit between the kicks of vv_step: no fused kicks
+  return run_loop(
+      s, user, nsteps, sample_every, thermo, false,
+      [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool, double* const*, double*) {
+        return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr, en, nullptr,
+                            pe_w, prec, slot);
+      },
+      &th);
 }
 
 // ------------------------------------------------------------ analysis

@@ -173,14 +173,25 @@ hipError_t lj_force_cells(const double* x, const double* y, const double* z,
                           int precision, bool energy, const ForceOut& out, hipStream_t st);
 
 // Velocity Verlet particle loops on the sorted state (INC on v and r).
+// Andersen collisions (Sec. 5.2) applied by vv_step right after the kick
+// that completes a step (modes 1 and 2), after the KE sample: particle s
+// collides with probability p and takes sd * (n1, n2, n3), the draws from
+// Philox4x64-10 with key (seed, 0) and counter (step, ids[s], block, 0).
+struct Andersen {
+  const int32_t* ids;  // particle ids of the slots: the random streams follow the particles
+  double p;            // collision probability per particle and step (nu dt); 0: none
+  double sd;           // sqrt(T / m)
+  uint64_t seed;
+  int64_t step;        // global index of the step that the kick completes
+};
 //   mode 0: v += h F ; r += dt v                          (first step)
-//   mode 1: v += h F ; [KE] ; v += h F ; r += dt v         (fused end+start)
-//   mode 2: v += h F ; [KE]                               (final half kick)
+//   mode 1: v += h F ; [KE] ; [collide] ; v += h F ; r += dt v   (fused end+start)
+//   mode 2: v += h F ; [KE] ; [collide]                   (final half kick)
 //   mode 3: KE only
 hipError_t vv_step(double* x, double* y, double* z, double* vx, double* vy, double* vz,
                    const void* fx, const void* fy, const void* fz, int precision, int64_t n,
                    double h, double dt, int mode, bool ke, double* ke_partials, uint32_t* flags,
-                   hipStream_t st, int* nblocks_out);
+                   hipStream_t st, int* nblocks_out, const Andersen* th = nullptr);
 
 // out[0] = sum of partials[k * stride + comp] over k, fixed order, one block.
 hipError_t reduce_partials(const double* partials, int nblocks, int stride, int ncomp,

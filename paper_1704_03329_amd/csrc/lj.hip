@@ -1,4 +1,4 @@
-// Lennard-Jones pair loop and velocity-Verlet particle loops.
+// Lennard-Jones pair loop with full neighbour lists (the default pair loop).
 //
 // Force (Eq. LJforce): f_ij = 48 eps [(s^2/d2)^7 - 1/2 (s^2/d2)^4] / s^2 * dr_ij,
 // dr_ij = r_i - r_j (min image), summed over the neighbour list of i and
@@ -237,165 +237,6 @@ hipError_t lj_force(const double* x, const double* y, const double* z, const int
       launch_force<float, double>(energy, st, x, y, z, cell_start, g, tl, c, out);
       break;
   }
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------ velocity Verlet
-// Listing position_update / velocity_update: v += F dt/(2m); r += dt v.
-template <typename FT>
-__global__ __launch_bounds__(256) void k_vv(double* __restrict__ x, double* __restrict__ y,
-                                            double* __restrict__ z, double* __restrict__ vx,
-                                            double* __restrict__ vy, double* __restrict__ vz,
-                                            const FT* __restrict__ fx, const FT* __restrict__ fy,
-                                            const FT* __restrict__ fz, int64_t n, double h,
-                                            double dt, int mode, int ke, double* ke_part,
-                                            uint32_t* flags) {
-#pragma clang fp contract(off)
-  __shared__ double sh[4];
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double k = 0.0;
-  if (s < n) {
-    double a = vx[s], b = vy[s], cc = vz[s];
-    if (mode != 3) {
-      const double gx = h * (double)fx[s], gy = h * (double)fy[s], gz = h * (double)fz[s];
-      a = a + gx;
-      b = b + gy;
-      cc = cc + gz;
-      if (mode == 1 || mode == 2) k = (a * a + b * b) + cc * cc;
-      if (mode == 1) {
-        a = a + gx;
-        b = b + gy;
-        cc = cc + gz;
-      }
-      if (mode != 2) {
-        x[s] = x[s] + dt * a;
-        y[s] = y[s] + dt * b;
-        z[s] = z[s] + dt * cc;
-      }
-      vx[s] = a;
-      vy[s] = b;
-      vz[s] = cc;
-      const double m2 = (a * a + b * b) + cc * cc;
-      if (!(m2 < 1e300)) atomicOr(flags, MDPL_FLAG_NONFINITE);
-    } else {
-      k = (a * a + b * b) + cc * cc;
-    }
-  }
-  if (ke) {
-    const double t = block_sum256(k, sh);
-    if (threadIdx.x == 0) ke_part[blockIdx.x] = t;
-  }
-}
-
-hipError_t vv_step(double* x, double* y, double* z, double* vx, double* vy, double* vz,
-                   const void* fx, const void* fy, const void* fz, int precision, int64_t n,
-                   double h, double dt, int mode, bool ke, double* ke_partials, uint32_t* flags,
-                   hipStream_t st, int* nblocks_out) {
-  const unsigned nb = (unsigned)div_up(n, 256);
-  if (nblocks_out) *nblocks_out = (int)nb;
-  if (precision == 1)
-    hipLaunchKernelGGL(k_vv<float>, dim3(nb), dim3(256), 0, st, x, y, z, vx, vy, vz,
-                       (const float*)fx, (const float*)fy, (const float*)fz, n, h, dt, mode,
-                       ke ? 1 : 0, ke_partials, flags);
-  else
-    hipLaunchKernelGGL(k_vv<double>, dim3(nb), dim3(256), 0, st, x, y, z, vx, vy, vz,
-                       (const double*)fx, (const double*)fy, (const double*)fz, n, h, dt, mode,
-                       ke ? 1 : 0, ke_partials, flags);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------ reductions
-// out[c] = scale * sum_k partials[k*stride + c], fixed order, one block.
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ p, int nb,
-                                                         int stride, int ncomp, double* out,
-                                                         double scale) {
-  __shared__ double sh[4];
-  for (int comp = 0; comp < ncomp; ++comp) {
-    double v = 0.0;
-    for (int k = threadIdx.x; k < nb; k += 256) v += p[(int64_t)k * stride + comp];
-    const double t = block_sum256(v, sh);
-    if (threadIdx.x == 0) out[comp] = scale * t;
-  }
-}
-
-hipError_t reduce_partials(const double* partials, int nblocks, int stride, int ncomp,
-                           double* out, double scale, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nblocks, stride,
-                     ncomp, out, scale);
-  return hipGetLastError();
-}
-
-}  // namespace mdpl
-
-namespace mdpl {
-
-// ------------------------------------------------------------ skin check
-// Largest squared displacement since the last list build, per block.
-__global__ __launch_bounds__(256) void k_disp_partials(
-    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ xb, const double* __restrict__ yb, const double* __restrict__ zb,
-    int64_t n, double* __restrict__ part) {
-  __shared__ double sh[4];
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double d = 0.0;
-  if (s < n) {
-    const double a = x[s] - xb[s], b = y[s] - yb[s], c = z[s] - zb[s];
-    d = a * a + b * b + c * c;
-    if (!(d < 1e300)) d = 1e300;
-  }
-  const double m = block_max256(d, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = m;
-}
-
-hipError_t disp_partials(const double* x, const double* y, const double* z, const double* xb,
-                         const double* yb, const double* zb, int64_t n, double* partials,
-                         hipStream_t st, int* nblocks_out) {
-  const unsigned nb = (unsigned)div_up(n, 256);
-  *nblocks_out = (int)nb;
-  hipLaunchKernelGGL(k_disp_partials, dim3(nb), dim3(256), 0, st, x, y, z, xb, yb, zb, n, partials);
-  return hipGetLastError();
-}
-
-// max over the partials -> displacement; record the largest; flag when it
-// reaches half the skin (a pair inside rc could then be missing from the list).
-__global__ __launch_bounds__(256) void k_skin_check(const double* __restrict__ part, int nb,
-                                                    double half_skin, double* max_disp,
-                                                    uint32_t* flags) {
-  __shared__ double sh[4];
-  double v = 0.0;
-  for (int k = threadIdx.x; k < nb; k += 256) v = part[k] > v ? part[k] : v;
-  const double m2 = block_max256(v, sh);
-  if (threadIdx.x == 0) {
-    const double d = sqrt(m2);
-    if (d > *max_disp) *max_disp = d;
-    if (d >= half_skin) atomicOr(flags, MDPL_FLAG_SKIN);
-  }
-}
-
-hipError_t skin_check(const double* partials, int nblocks, double half_skin, double* max_disp,
-                      uint32_t* flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_skin_check, dim3(1), dim3(256), 0, st, partials, nblocks, half_skin,
-                     max_disp, flags);
-  return hipGetLastError();
-}
-
-}  // namespace mdpl
-
-namespace mdpl {
-
-__global__ void k_scale_v(double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
-                          int64_t n, double f) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  vx[i] *= f;
-  vy[i] *= f;
-  vz[i] *= f;
-}
-
-hipError_t scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_v, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, vx, vy, vz, n,
-                     factor);
   return hipGetLastError();
 }
 

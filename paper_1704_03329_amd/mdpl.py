@@ -70,6 +70,7 @@ _SIGS = {
     "mdpl_forces": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "mdpl_lj_backward": ([_P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "mdpl_run": ([_P] + [_P] * 10 + [_I64, _I32, _P], _I32),
+    "mdpl_run_andersen": ([_P] + [_P] * 10 + [_I64, _I32, _P, _D, _D, ctypes.c_uint64, _I64], _I32),
     "mdpl_check": ([_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_I32)], _I32),
     "mdpl_clear_flags": ([_P], _I32),
     "mdpl_set_timing": ([_P, _I32], _I32),
@@ -204,6 +205,14 @@ def mdpl_run(sim: int, x, y, z, vx, vy, vz, fx, fy, fz, ids, nsteps: int, sample
     _check(lib().mdpl_run(sim, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(fx),
                           _ptr(fy), _ptr(fz), _ptr(ids), int(nsteps), int(sample_every), _ptr(thermo)),
            "mdpl_run")
+
+
+def mdpl_run_andersen(sim: int, x, y, z, vx, vy, vz, fx, fy, fz, ids, nsteps: int, sample_every: int,
+                      thermo, temperature: float, collision_rate: float, seed: int, step0: int = 0):
+    _check(lib().mdpl_run_andersen(sim, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(fx),
+                                   _ptr(fy), _ptr(fz), _ptr(ids), int(nsteps), int(sample_every),
+                                   _ptr(thermo), float(temperature), float(collision_rate),
+                                   int(seed) & ((1 << 64) - 1), int(step0)), "mdpl_run_andersen")
 
 
 def mdpl_check(sim: int, raise_on_error: bool = False):

@@ -79,13 +79,20 @@ class LJSim:
         return {"x": x, "y": y, "z": z, "vx": vx, "vy": vy, "vz": vz, "fx": f[0], "fy": f[1], "fz": f[2],
                 "ids": ids}
 
-    def run(self, state, nsteps, sample_every=0):
+    def run(self, state, nsteps, sample_every=0, andersen=None):
+        """nsteps of velocity Verlet; andersen: optional dict(temperature,
+        collision_rate, seed, step0) for mdpl_run_andersen."""
         thermo = None
         if sample_every:
             thermo = torch.zeros((nsteps // sample_every + 1, 4), dtype=torch.float64, device=self.device)
         s = state
-        C.mdpl_run(self.handle, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["fx"], s["fy"], s["fz"],
-                   s["ids"], nsteps, sample_every, thermo)
+        args = (self.handle, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["fx"], s["fy"], s["fz"],
+                s["ids"], nsteps, sample_every, thermo)
+        if andersen is None:
+            C.mdpl_run(*args)
+        else:
+            C.mdpl_run_andersen(*args, andersen["temperature"], andersen["collision_rate"], andersen["seed"],
+                                andersen.get("step0", 0))
         return thermo
 
     def check(self, raise_on_error=True):
