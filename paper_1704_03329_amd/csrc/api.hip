@@ -153,7 +153,31 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += align256(4 * (size_t)(n + 1));          // offsets
   b += align256(8 * (size_t)(3 * nblk + 2));   // partials
   b += align256(64);                           // flags, maxcount, max_disp, pe_w_tmp
+  b += align256(4 * (size_t)(((g.nbricks + 7) / 8) * 8));  // brick order of the tile kernels
   return b;
+}
+
+// Workgroup -> brick of the tile kernels: workgroup w runs on XCD w mod 8;
+// XCD x takes the slab of bricks [x per, (x+1) per) (contiguous, so that
+// tiles reload from its own L2), its full bricks first and then the thin
+// ones (last along an axis whose cell count B does not divide), so that the
+// light workgroups fill the last round.  Padding entries hold nbricks.
+std::vector<int32_t> brick_order(const Grid& g) {
+  const int per = (g.nbricks + 7) / 8;
+  std::vector<int32_t> order((size_t)per * 8, g.nbricks);
+  auto thin = [&](int b) {
+    const int bx = b % g.nb[0], by = (b / g.nb[0]) % g.nb[1], bz = b / (g.nb[0] * g.nb[1]);
+    return (bx == g.nb[0] - 1 && g.nc[0] % g.B[0]) || (by == g.nb[1] - 1 && g.nc[1] % g.B[1]) ||
+           (bz == g.nb[2] - 1 && g.nc[2] % g.B[2]);
+  };
+  for (int x = 0; x < 8; ++x) {
+    int j = 0;
+    const int lo = x * per, hi = (x + 1) * per < g.nbricks ? (x + 1) * per : g.nbricks;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int b = lo; b < hi; ++b)
+        if (thin(b) == (pass == 1)) order[(size_t)j++ * 8 + x] = b;
+  }
+  return order;
 }
 
 template <typename T>
@@ -298,6 +322,17 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
   s->partials = take<double>(w, 8 * (size_t)(3 * s->nblk + 2));
   char* small = take<char>(w, 64);
+  {
+    const std::vector<int32_t> order = brick_order(s->g);
+    int32_t* dorder = take<int32_t>(w, 4 * order.size());
+    const hipError_t e = hipMemcpy(dorder, order.data(), 4 * order.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      g_last_hip_error = (int32_t)e;
+      delete s;
+      return MDPL_EHIP;
+    }
+    s->g.order = dorder;
+  }
   s->flags = (uint32_t*)small;
   s->maxcount = (int32_t*)(small + 4);
   s->max_disp = (double*)(small + 8);

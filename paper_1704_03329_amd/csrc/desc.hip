@@ -133,7 +133,7 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
                                                    const int32_t* __restrict__ cs, Grid g,
                                                    TileList tl, float rc, DescIO io) {
   __shared__ TileShared t;
-  const int brick = brick_of_block(g.nbricks);
+  const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
   tile_load<true>(g, x, y, z, total, t);
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
                                                    TileList tl, float rc, DescIO io) {
   __shared__ TileShared t;
   __shared__ float acc[3][kTileMax];
-  const int brick = brick_of_block(g.nbricks);
+  const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
   const int nt = total < kTileCap ? total : kTileCap;

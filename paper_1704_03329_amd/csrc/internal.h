@@ -35,6 +35,9 @@ struct Grid {
   int nkeys;  // nbricks * V
   double inv_side[3];
   double box[3];
+  // tile kernels: brick of each workgroup (device, tile_grid_blocks(nbricks)
+  // entries, nbricks for padding); null: the order of brick_of_block
+  const int32_t* order;
 };
 
 // Returns MDPL_EBOX if fewer than 3 cells fit along some axis.

@@ -67,7 +67,7 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
                 LJConst c, ForceOut out) {
   __shared__ TileShared t;
   __shared__ double red[48];  // up to 16 waves: e, w, ke
-  const int brick = brick_of_block(g.nbricks);
+  const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
   tile_load<true>(g, x, y, z, total, t);

@@ -52,7 +52,7 @@ void k_lj_force_half(const double* __restrict__ x, const double* __restrict__ y,
   __shared__ typename A::T acc[3][kTileMaxHalf];
   __shared__ double acce[EATOM ? kTileMaxHalf : 1];
   __shared__ double red[32];  // up to 16 waves: e, w
-  const int brick = brick_of_block(g.nbricks);
+  const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t, true);
   const int nt = total < TileHalf::kCap ? total : TileHalf::kCap;
@@ -204,7 +204,7 @@ void k_lj_force_cells(const double* __restrict__ x, const double* __restrict__ y
                       LJConst c, ForceOut out) {
   __shared__ TileShared t;
   __shared__ double red[32];  // up to 16 waves: e, w
-  const int brick = brick_of_block(g.nbricks);
+  const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
   if (threadIdx.x == 0 && total > kTileCap) atomicOr(out.flags, MDPL_FLAG_NL_OVERFLOW);

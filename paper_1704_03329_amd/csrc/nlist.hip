@@ -116,7 +116,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     float guard, TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
   __shared__ TS t;
   __shared__ int acnt[kBrickMax];
-  const int brick = brick_of_block(g.nbricks);
+  const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t, HALF);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(1024) void k_export_tile_pairs(
     const int32_t* __restrict__ offsets, int32_t* __restrict__ i_out, int32_t* __restrict__ j_out,
     int64_t cap) {
   __shared__ TileCells t;
-  const int brick = brick_of_block(g.nbricks);
+  const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   tile_cells(g, brick, cs, t, tl.half != 0);
   const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);

@@ -56,8 +56,13 @@ using TileHalf32 = TileOf<float, kTileMaxHalf>;
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // run of bricks (a slab of the box) so that tile reloads hit its own L2.
-__device__ __forceinline__ int brick_of_block(int nbricks) {
-  const int per = (nbricks + 7) >> 3;
+// With a brick order (built on the host, see brick_order), each XCD takes its
+// slab's full bricks first and the thin ones (the last brick along an axis
+// whose cell count is not a multiple of B) last, so that light workgroups
+// fill the final round.  Returns nbricks for padding workgroups.
+__device__ __forceinline__ int brick_of_block(const Grid& g) {
+  if (g.order) return g.order[blockIdx.x];
+  const int per = (g.nbricks + 7) >> 3;
   return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
 }
 
