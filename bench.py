@@ -31,6 +31,11 @@ METRIC = "atom-steps/s LJ N=1M + HBM GB/s; MLP vs LJ time at stated force RMSE"
 HBM_PEAK_GBS = 8000.0
 FORCE_SRC = os.path.join(ROOT, "paper_1704_03329_amd", "csrc", "lj.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lj_force_f32_n1m_traffic.txt")
+FLOPS_FILE = os.path.join(ROOT, "profiles", "lj_force_f32_n1m_flops.txt")
+# vector (non-matrix) peaks: 256 CUs x 2.4 GHz x 64 lanes x 2 (fused multiply-add) for FP64 and
+# for unpacked FP32; the FP32 figure doubles with packed two-wide instructions
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -42,23 +47,57 @@ def force_src_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per force launch from the committed counter summary, or None
-    if absent or taken on a different version of the force kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
+def counter_summary(path):
+    """The key: value lines of a committed counter summary, or None if it is
+    absent or was taken on a different version of the force kernel."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("force_source_sha256_16") != force_src_hash():
         return None
+    return kv
+
+
+def measured_traffic():
+    """HBM bytes per force launch from the committed counter summary."""
+    kv = counter_summary(TRAFFIC_FILE)
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+def measured_flops(avg_s, entries):
+    """FP32 and FP64 vector FLOP rates of the plain force kernel: the counted
+    FLOPs per launch from the committed counter summary over the launch time
+    measured in this run (None if the summary does not match the kernel)."""
+    kv = counter_summary(FLOPS_FILE)
+    if not kv:
+        return None
+    try:
+        f32 = float(kv["fp32_flops_per_launch"]) + float(kv["fp32_trans_per_launch"])
+        f64 = float(kv["fp64_flops_per_launch"]) + float(kv["fp64_trans_per_launch"])
+        valu = float(kv["valu_insts_per_entry"])
+        ent = float(kv["entries_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    # the summary's launches start from the lattice (more entries than the
+    # timed run); scale the counted work to this run's entry count
+    k = entries / ent if ent > 0 else 1.0
+    t32, t64 = f32 * k / avg_s / 1e12, f64 * k / avg_s / 1e12
+    # vector issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
+    issue = valu * entries / avg_s / (256 * 64 * 2.4e9)
+    return {"fp32_tflops": t32, "fp64_tflops": t64, "unit": "TFLOP/s",
+            "peak_fp32": FP32_PEAK_TFLOPS, "peak_fp64": FP64_PEAK_TFLOPS,
+            "frac_fp32": t32 / FP32_PEAK_TFLOPS, "frac_fp64": t64 / FP64_PEAK_TFLOPS,
+            "fp32_flops_per_entry": f32 / ent, "fp64_flops_per_entry": f64 / ent,
+            "valu_insts_per_entry": valu, "valu_issue_frac": issue,
+            "source": "rocprofv3 SQ_INSTS_VALU_FLOPS_* counters (profiles/lj_force_f32_n1m_flops.txt)"}
 
 
 def cpu_baseline(pos, box, rows: int):
@@ -288,6 +327,9 @@ def main():
                     help="skip the short runs of the other pair loops reported beside the main one")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one elementwise copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--flop-probe-m", type=int, default=0,
+                    help="first run one elementwise FP32 and one FP64 product over this many "
+                         "Mi elements (FLOP counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -310,6 +352,14 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: one elementwise kernel reading and writing {args.copy_probe_mib} MiB each")
         del src, dst
+    if args.flop_probe_m:
+        for dt in (torch.float32, torch.float64):
+            a = torch.full((args.flop_probe_m << 20,), 1.5, dtype=dt, device=dev)
+            b = torch.full_like(a, 0.75)
+            torch.mul(a, b, out=a)
+            torch.cuda.synchronize()
+            del a, b
+        log(f"flop probe: one FP32 and one FP64 product over {args.flop_probe_m} Mi elements each")
     n_side = args.n_side
     d = mdinputs.lj_fluid(n_side, temperature=1.0, seed=2)
     n = d["pos"].shape[0]
@@ -371,6 +421,7 @@ def main():
     avg_s = (f_ms / 1e3) / max(f_n, 1)
     achieved = alg_bytes / avg_s / 1e9
     traffic = measured_traffic() if args.pairs == "full" else None
+    flops = measured_flops(avg_s, entries) if args.pairs == "full" else None
 
     out = {
         "metric": METRIC,
@@ -411,6 +462,7 @@ def main():
             "avg_launch_us": avg_s * 1e6,
             "launches": f_n,
         },
+        "flops": flops,
         "kernels_us": {
             "force": avg_s * 1e6,
             "force_energy_virial": (fe_ms / max(fe_n, 1)) * 1e3,
