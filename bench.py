@@ -29,7 +29,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s LJ N=1M + HBM GB/s; MLP vs LJ time at stated force RMSE"
 HBM_PEAK_GBS = 8000.0
-FORCE_SRC = os.path.join(ROOT, "paper_1704_03329_amd", "csrc", "lj.hip")
+# every source the force kernel is compiled from (counter summaries name their hash)
+FORCE_SRC = [os.path.join(ROOT, "paper_1704_03329_amd", "csrc", f)
+             for f in ("lj.hip", "tile.h", "device_util.h", "internal.h")] + \
+    [os.path.join(ROOT, "include", "mdpl.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lj_force_f32_n1m_traffic.txt")
 FLOPS_FILE = os.path.join(ROOT, "profiles", "lj_force_f32_n1m_flops.txt")
 # vector (non-matrix) peaks: 256 CUs x 2.4 GHz x 64 lanes x 2 (fused multiply-add) for FP64 and
@@ -43,8 +46,11 @@ def log(msg):
 
 
 def force_src_hash() -> str:
-    with open(FORCE_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in FORCE_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_summary(path):

@@ -129,7 +129,7 @@ void k_lj_force_half(const double* __restrict__ x, const double* __restrict__ y,
             A::add(&acc[1][u], -py);
             A::add(&acc[2][u], -pz);
           } else {  // too large for the accumulator: straight to the output
-            const int cell = tile_cell_of(t, (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2), u);
+            const int cell = t.cell[u];
             const int slot = t.src[cell] + (u - t.prefix[cell]);
             const int64_t o = out.scatter ? (int64_t)out.scatter[slot] : (int64_t)slot;
             unsafeAtomicAdd(&fx[o], (OT)(-px * scale));
@@ -152,12 +152,11 @@ void k_lj_force_half(const double* __restrict__ x, const double* __restrict__ y,
     if (EATOM) unsafeAtomicAdd(&out.e_atom[o], ei);
   }
   __syncthreads();
-  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
     const double ux = A::get(acc[0][u]), uy = A::get(acc[1][u]), uz = A::get(acc[2][u]);
     const double ue = EATOM ? acce[u] : 0.0;
     if (ux == 0.0 && uy == 0.0 && uz == 0.0 && ue == 0.0) continue;  // never a partner here
-    const int cell = tile_cell_of(t, ntc, u);
+    const int cell = t.cell[u];
     const int slot = t.src[cell] + (u - t.prefix[cell]);
     const int64_t o = out.scatter ? (int64_t)out.scatter[slot] : (int64_t)slot;
     unsafeAtomicAdd(&fx[o], (OT)(ux * scale));

@@ -56,7 +56,7 @@ struct RowScan {
   double xs, ys, zs;           // its stored FP64 position (exact test)
   const double *x, *y, *z;     // stored FP64 positions, sorted slots
   double r2, Lx, Ly, Lz, hx, hy, hz;
-  int self, K, max_nb, ntc;
+  int self, K, max_nb;
   int* cnt;                    // the particle's LDS counter
   uint16_t* base;              // its list: entry m at base[(m >> 2) * stride4 + (m & 3)]
   uint32_t stride4;
@@ -87,7 +87,7 @@ __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const Ro
       bool acc = other && d2f < q.r2lo;
       if (other && !(d2f < q.r2lo) && d2f <= q.r2hi) {
         // inside the guard band: the definition decides
-        const int c = tile_cell_of(t, q.ntc, uu[j]);
+        const int c = t.cell[uu[j]];
         const int sj = t.src[c] + (uu[j] - t.prefix[c]);
         acc = exact_d2(q.xs, q.ys, q.zs, q.x[sj], q.y[sj], q.z[sj], q.Lx, q.Ly, q.Lz, q.hx, q.hy,
                        q.hz) < q.r2;
@@ -133,6 +133,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   const double ox = (double)(bx * g.B[0] - 1) * (Lx / g.nc[0]);
   const double oy = (double)(by * g.B[1] - 1) * (Ly / g.nc[1]);
   const double oz = (double)(bz * g.B[2] - 1) * (Lz / g.nc[2]);
+  tile_slot_cells(ntc, total, t);
   {
     const int nt = total < TS::kCap ? total : TS::kCap;
     if (threadIdx.x == 0) {
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       t.z[TS::kDummy] = kFarF;
     }
     for (int u = threadIdx.x; u < nt; u += blockDim.x) {
-      const int c = tile_cell_of(t, ntc, u);
+      const int c = t.cell[u];
       const int src = t.src[c] + (u - t.prefix[c]);
       const int code = t.code[c];
       t.x[u] = (float)((x[src] + (double)((code & 3) - 1) * Lx) - ox);
@@ -195,7 +196,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       q.self = self;
       q.K = K;
       q.max_nb = max_nb;
-      q.ntc = ntc;
       q.cnt = &acnt[ok ? la : 0];
       q.base = half + (int64_t)(ok ? s : 0) * 4;
       q.stride4 = (uint32_t)(tl.stride * 4);

@@ -39,7 +39,9 @@ struct TileOf {
   int prefix[kTileCells + 1];
   int src[kTileCells];
   int code[kTileCells];
+  uint8_t cell[CAP];  // tile cell of each filled slot (tile_slot_cells)
 };
+static_assert(kTileCells <= 256, "a tile cell index must fit the byte map");
 // the cell table alone (kernels that map tile indices to slots only)
 struct TileCells {
   int prefix[kTileCells + 1];
@@ -120,26 +122,36 @@ __device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __rest
   return t.prefix[ntc];
 }
 
+// Fills the byte map t.cell[u] = tile cell of slot u for the first
+// min(total, TS::kCap) slots, eight threads per cell, so that a slot finds
+// its cell with one LDS read instead of a search over the prefix.  Ends
+// with a barrier.
+template <typename TS>
+__device__ inline void tile_slot_cells(int ntc, int total, TS& t) {
+  const int nt = total < TS::kCap ? total : TS::kCap;
+  for (int tc = (int)threadIdx.x >> 3; tc < ntc; tc += (int)blockDim.x >> 3) {
+    const int e = t.prefix[tc + 1] < nt ? t.prefix[tc + 1] : nt;
+    for (int u = t.prefix[tc] + ((int)threadIdx.x & 7); u < e; u += 8) t.cell[u] = (uint8_t)tc;
+  }
+  __syncthreads();
+}
+
 // Copies the tile's positions (at most TS::kCap) into LDS; IMAGE adds the
-// periodic image offsets.  Ends with a barrier.
+// periodic image offsets.  Fills the slot map first.  Ends with a barrier.
 template <bool IMAGE, typename TS>
 __device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
                                  const double* __restrict__ y, const double* __restrict__ z,
                                  int total, TS& t) {
   const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
   const int nt = total < TS::kCap ? total : TS::kCap;
+  tile_slot_cells(ntc, total, t);
   if (threadIdx.x == 0) {  // padding slot: no pair with it is ever inside the cutoff
     t.x[TS::kDummy] = 1e20;
     t.y[TS::kDummy] = 1e20;
     t.z[TS::kDummy] = 1e20;
   }
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
-    int lo = 0, hi = ntc;  // prefix[lo] <= u < prefix[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (t.prefix[mid] <= u) lo = mid;
-      else hi = mid;
-    }
+    const int lo = t.cell[u];
     const int src = t.src[lo] + (u - t.prefix[lo]);
     double a = x[src], b = y[src], c = z[src];
     if (IMAGE) {
@@ -156,7 +168,8 @@ __device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
 }
 
 // Tile cell of tile particle u < total (binary search over the prefix;
-// a tile has at least 27 cells, so the first halving always happens).
+// a tile has at least 27 cells, so the first halving always happens), for
+// tables without the slot map.
 template <typename TS>
 __device__ __forceinline__ int tile_cell_of(const TS& t, int ntc, int u) {
   int lo = 0, hi = ntc;  // prefix[lo] <= u < prefix[hi]
