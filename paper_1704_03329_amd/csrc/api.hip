@@ -153,30 +153,44 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += align256(4 * (size_t)(n + 1));          // offsets
   b += align256(8 * (size_t)(3 * nblk + 2));   // partials
   b += align256(64);                           // flags, maxcount, max_disp, pe_w_tmp
-  b += align256(4 * (size_t)(((g.nbricks + 7) / 8) * 8));  // brick order of the tile kernels
+  b += align256(4 * 8 * (size_t)g.nbricks);   // brick order of the tile kernels
   return b;
 }
 
-// Workgroup -> brick of the tile kernels: workgroup w runs on XCD w mod 8;
-// XCD x takes the slab of bricks [x per, (x+1) per) (contiguous, so that
-// tiles reload from its own L2), its full bricks first and then the thin
-// ones (last along an axis whose cell count B does not divide), so that the
-// light workgroups fill the last round.  Padding entries hold nbricks.
-std::vector<int32_t> brick_order(const Grid& g) {
-  const int per = (g.nbricks + 7) / 8;
-  std::vector<int32_t> order((size_t)per * 8, g.nbricks);
-  auto thin = [&](int b) {
-    const int bx = b % g.nb[0], by = (b / g.nb[0]) % g.nb[1], bz = b / (g.nb[0] * g.nb[1]);
-    return (bx == g.nb[0] - 1 && g.nc[0] % g.B[0]) || (by == g.nb[1] - 1 && g.nc[1] % g.B[1]) ||
-           (bz == g.nb[2] - 1 && g.nc[2] % g.B[2]);
-  };
-  for (int x = 0; x < 8; ++x) {
-    int j = 0;
-    const int lo = x * per, hi = (x + 1) * per < g.nbricks ? (x + 1) * per : g.nbricks;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int b = lo; b < hi; ++b)
-        if (thin(b) == (pass == 1)) order[(size_t)j++ * 8 + x] = b;
+static bool thin_brick(const Grid& g, int b) {
+  const int bx = b % g.nb[0], by = (b / g.nb[0]) % g.nb[1], bz = b / (g.nb[0] * g.nb[1]);
+  return (bx == g.nb[0] - 1 && g.nc[0] % g.B[0]) || (by == g.nb[1] - 1 && g.nc[1] % g.B[1]) ||
+         (bz == g.nb[2] - 1 && g.nc[2] % g.B[2]);
+}
+
+// The bricks of the 8 XCDs.  Workgroup w goes to XCD w mod 8 in dispatch
+// order, so each round of 8 consecutive workgroups should carry equal work:
+// the full bricks, in index order (z slowest), are dealt out in 8
+// contiguous pieces (slabs of the box, whose tiles reload from the XCD's own
+// L2), then the thin ones (the last brick along an axis whose cell count B
+// does not divide) the same way, so that every XCD gets the same mix.
+static std::vector<std::vector<int32_t>> xcd_bricks(const Grid& g) {
+  std::vector<int32_t> full, thin;
+  for (int b = 0; b < g.nbricks; ++b) (thin_brick(g, b) ? thin : full).push_back(b);
+  std::vector<std::vector<int32_t>> xcd(8);
+  for (const std::vector<int32_t>* v : {&full, &thin}) {
+    const size_t per = (v->size() + 7) / 8;
+    for (size_t k = 0; k < v->size(); ++k) xcd[k / per].push_back((*v)[k]);
   }
+  return xcd;
+}
+
+// Workgroup -> brick of the tile kernels: workgroup w runs on XCD w mod 8;
+// XCD x takes its bricks (xcd_bricks), the full ones first and then the thin
+// ones, so that the light workgroups fill the last round.  8 entries per
+// round; padding entries hold nbricks.
+std::vector<int32_t> brick_order(const Grid& g) {
+  const std::vector<std::vector<int32_t>> xcd = xcd_bricks(g);
+  size_t most = 0;
+  for (const auto& v : xcd) most = v.size() > most ? v.size() : most;
+  std::vector<int32_t> order(most * 8, g.nbricks);
+  for (int x = 0; x < 8; ++x)
+    for (size_t j = 0; j < xcd[x].size(); ++j) order[j * 8 + x] = xcd[x][j];
   return order;
 }
 
@@ -324,7 +338,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   char* small = take<char>(w, 64);
   {
     const std::vector<int32_t> order = brick_order(s->g);
-    int32_t* dorder = take<int32_t>(w, 4 * order.size());
+    int32_t* dorder = take<int32_t>(w, 4 * 8 * (size_t)s->g.nbricks);
     const hipError_t e = hipMemcpy(dorder, order.data(), 4 * order.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       g_last_hip_error = (int32_t)e;
@@ -332,6 +346,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
       return MDPL_EHIP;
     }
     s->g.order = dorder;
+    s->g.norder = (int)order.size();
   }
   s->flags = (uint32_t*)small;
   s->maxcount = (int32_t*)(small + 4);

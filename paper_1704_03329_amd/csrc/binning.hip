@@ -16,6 +16,7 @@ namespace mdpl {
 mdpl_status make_grid(const double box[3], double r, const int brick[3], Grid* g) {
   g->nbricks = 1;
   g->order = nullptr;
+  g->norder = 0;
   for (int k = 0; k < 3; ++k) {
     double side_min = r * (1.0 + 1e-10);
     double q = floor(box[k] / side_min);

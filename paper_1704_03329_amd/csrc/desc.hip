@@ -421,7 +421,7 @@ hipError_t desc_forward(const double* x, const double* y, const double* z,
                         const int32_t* perm, float* G, float* mom, hipStream_t st) {
   DescIO io{G, mom, nullptr, perm, nullptr, nullptr, nullptr};
   const unsigned threads = tl.threads < 512 ? tl.threads : 512;
-  hipLaunchKernelGGL(k_desc_fwd, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st, x, y,
+  hipLaunchKernelGGL(k_desc_fwd, dim3(tile_grid(g)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);
   return hipGetLastError();
 }
@@ -433,7 +433,7 @@ hipError_t desc_backward(const double* x, const double* y, const double* z,
   DescIO io{nullptr, const_cast<float*>(mom), dEdG, perm, fx, fy, fz};
   hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
   const unsigned threads = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
-  hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid_blocks(g.nbricks)), dim3(threads), 0, st, x, y,
+  hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid(g)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);
   return hipGetLastError();
 }

@@ -35,9 +35,10 @@ struct Grid {
   int nkeys;  // nbricks * V
   double inv_side[3];
   double box[3];
-  // tile kernels: brick of each workgroup (device, tile_grid_blocks(nbricks)
-  // entries, nbricks for padding); null: the order of brick_of_block
+  // tile kernels: brick of each of their norder workgroups (device, nbricks
+  // for padding); null: the order of brick_of_block
   const int32_t* order;
+  int norder;
 };
 
 // Returns MDPL_EBOX if fewer than 3 cells fit along some axis.

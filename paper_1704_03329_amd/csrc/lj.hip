@@ -208,7 +208,7 @@ template <typename MT, typename OT>
 static void launch_force(bool energy, hipStream_t st, const double* x, const double* y,
                          const double* z, const int32_t* cs, const Grid& g, const TileList& tl,
                          const LJConst& c, const ForceOut& out) {
-  const dim3 grid(tile_grid_blocks(g.nbricks));
+  const dim3 grid(tile_grid(g));
   const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
   if (energy)
     hipLaunchKernelGGL((k_lj_force<MT, OT, true>), grid, dim3(two), 0, st, x, y, z, cs, g, tl, c, out);

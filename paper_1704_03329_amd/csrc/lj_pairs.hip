@@ -334,7 +334,7 @@ template <typename MT, typename OT>
 static void launch_half(bool energy, hipStream_t st, const double* x, const double* y,
                         const double* z, const int32_t* cs, const Grid& g, const TileList& tl,
                         const LJConst& c, const ForceOut& out, int64_t n) {
-  const dim3 grid(tile_grid_blocks(g.nbricks));
+  const dim3 grid(tile_grid(g));
   const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
   // outputs accumulate with atomics: clear them first (caller order, n entries)
   const dim3 zb((unsigned)div_up(n, 256));
@@ -356,7 +356,7 @@ template <typename MT, typename OT>
 static void launch_cells(bool energy, hipStream_t st, const double* x, const double* y,
                          const double* z, const int32_t* cs, const Grid& g, const LJConst& c,
                          const ForceOut& out) {
-  const dim3 grid(tile_grid_blocks(g.nbricks));
+  const dim3 grid(tile_grid(g));
   const unsigned waves = g.V * 64 < 1024 ? (unsigned)g.V * 64 : 1024u;  // one wave per home cell
   if (energy)
     hipLaunchKernelGGL((k_lj_force_cells<MT, OT, true>), grid, dim3(waves), 0, st, x, y, z, cs, g,

@@ -251,7 +251,7 @@ hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
   const double rext = sqrt(r2);
   const double err = 2.0 * sqrt(3.0) * rext * u32 * (2.0 * span + 2.0 * rext) + 3.0 * u32 * r2;
   const float guard = (float)(8.0 * err);
-  const dim3 grid(tile_grid_blocks(g.nbricks));
+  const dim3 grid(tile_grid(g));
   if (tl.half)
     hipLaunchKernelGGL((k_build_tile_nlist<TileHalf32, true>), grid, dim3(threads), 0, st, x, y, z,
                        skeys, cell_start, g, r2, guard, tl, flags, maxcount);
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(1024) void k_export_tile_pairs(
 hipError_t export_tile_pairs(const TileList& tl, const int32_t* cell_start, const Grid& g,
                              const int32_t* perm, const int32_t* offsets, int32_t* i_out,
                              int32_t* j_out, int64_t cap, hipStream_t st) {
-  hipLaunchKernelGGL(k_export_tile_pairs, dim3(tile_grid_blocks(g.nbricks)), dim3(tl.threads), 0,
+  hipLaunchKernelGGL(k_export_tile_pairs, dim3(tile_grid(g)), dim3(tl.threads), 0,
                      st, tl, cell_start, g, perm, offsets, i_out, j_out, cap);
   return hipGetLastError();
 }

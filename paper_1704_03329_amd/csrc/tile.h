@@ -58,9 +58,10 @@ using TileHalf32 = TileOf<float, kTileMaxHalf>;
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // run of bricks (a slab of the box) so that tile reloads hit its own L2.
-// With a brick order (built on the host, see brick_order), each XCD takes its
-// slab's full bricks first and the thin ones (the last brick along an axis
-// whose cell count is not a multiple of B) last, so that light workgroups
+// With a brick order (built on the host, see brick_order), the full bricks
+// and then the thin ones (the last brick along an axis whose cell count is
+// not a multiple of B) are each dealt to the XCDs in 8 contiguous pieces, so
+// that every round of 8 workgroups carries equal work and light workgroups
 // fill the final round.  Returns nbricks for padding workgroups.
 __device__ __forceinline__ int brick_of_block(const Grid& g) {
   if (g.order) return g.order[blockIdx.x];
@@ -68,7 +69,11 @@ __device__ __forceinline__ int brick_of_block(const Grid& g) {
   return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
 }
 
-inline unsigned tile_grid_blocks(int nbricks) { return (unsigned)(((nbricks + 7) >> 3) * 8); }
+// Workgroups of a tile kernel: the brick order's length, else one per brick
+// rounded up to whole rounds of the 8 XCDs.
+inline unsigned tile_grid(const Grid& g) {
+  return g.order ? (unsigned)g.norder : (unsigned)(((g.nbricks + 7) >> 3) * 8);
+}
 
 __device__ __forceinline__ void brick_coords(const Grid& g, int brick, int& bx, int& by, int& bz) {
   bx = brick % g.nb[0];
