@@ -22,6 +22,8 @@
 // Potential energy: PE = 1/2 sum over ordered pairs (each unordered pair
 // once), e_i = 1/2 sum_j V(r_ij); virial W = 1/2 sum over ordered pairs of
 // dr . f.
+#include <type_traits>
+
 #include "device_util.h"
 #include "internal.h"
 #include "tile.h"
@@ -65,12 +67,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
                 const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g, TileList tl,
                 LJConst c, ForceOut out) {
-  __shared__ TileShared t;
+  // plain pass: x and y side by side (one 16-byte gather per entry, measured
+  // faster); energy pass: three arrays (measured faster there)
+  using Tile = std::conditional_t<ENERGY, TileShared, TileXY>;
+  __shared__ Tile t;
   __shared__ double red[48];  // up to 16 waves: e, w, ke
   const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
-  tile_load<true>(g, x, y, z, total, t);
+  if constexpr (ENERGY) tile_load<true>(g, x, y, z, total, t);
+  else tile_load_xy(g, x, y, z, total, t);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   // plain pass: f_ij / dr_ij = x^4 (A x^3 - B) with x = 1 / d2, A = 48 eps s^12, B = 24 eps s^6
   const double sig6 = c.sigma2 * c.sigma2 * c.sigma2;
@@ -102,9 +108,15 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
       constexpr bool kAhead = !ENERGY && sizeof(MT) == 4;
       double qx, qy, qz;
       auto tile_pos = [&](int k) {
-        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;  // byte offset in a tile array
-        qx = *(const double*)((const char*)t.x + off);
-        qy = *(const double*)((const char*)t.y + off);
+        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;  // byte offset in t.z
+        if constexpr (ENERGY) {
+          qx = *(const double*)((const char*)t.x + off);
+          qy = *(const double*)((const char*)t.y + off);
+        } else {
+          const double2 q = *(const double2*)((const char*)t.xy + 2 * off);
+          qx = q.x;
+          qy = q.y;
+        }
         qz = *(const double*)((const char*)t.z + off);
       };
       tile_pos(0);

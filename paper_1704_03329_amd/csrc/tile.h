@@ -42,6 +42,20 @@ struct TileOf {
   uint8_t cell[CAP];  // tile cell of each filled slot (tile_slot_cells)
 };
 static_assert(kTileCells <= 256, "a tile cell index must fit the byte map");
+// full-list force pass: x and y of a slot side by side (one 16-byte read),
+// z apart; list entries stay byte offsets into the 8-byte z array
+template <int CAP>
+struct TileXYOf {
+  static constexpr int kSlots = CAP;
+  static constexpr int kDummy = CAP - 1;
+  static constexpr int kCap = CAP - 1;
+  double2 xy[CAP];
+  double z[CAP];
+  int prefix[kTileCells + 1];
+  int src[kTileCells];
+  int code[kTileCells];
+  uint8_t cell[CAP];
+};
 // the cell table alone (kernels that map tile indices to slots only)
 struct TileCells {
   int prefix[kTileCells + 1];
@@ -55,6 +69,7 @@ using TileShared32 = TileOf<float, kTileMax>;
 // half lists: the same with the capacity of a half tile
 using TileHalf = TileOf<double, kTileMaxHalf>;
 using TileHalf32 = TileOf<float, kTileMaxHalf>;
+using TileXY = TileXYOf<kTileMax>;
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // run of bricks (a slab of the box) so that tile reloads hit its own L2.
@@ -168,6 +183,29 @@ __device__ inline void tile_load(const Grid& g, const double* __restrict__ x,
     t.x[u] = a;
     t.y[u] = b;
     t.z[u] = c;
+  }
+  __syncthreads();
+}
+
+// tile_load for the x-y paired tile (image positions).  Ends with a barrier.
+template <int CAP>
+__device__ inline void tile_load_xy(const Grid& g, const double* __restrict__ x,
+                                    const double* __restrict__ y, const double* __restrict__ z,
+                                    int total, TileXYOf<CAP>& t) {
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int nt = total < TileXYOf<CAP>::kCap ? total : TileXYOf<CAP>::kCap;
+  tile_slot_cells(ntc, total, t);
+  if (threadIdx.x == 0) {  // padding slot: no pair with it is ever inside the cutoff
+    t.xy[TileXYOf<CAP>::kDummy] = make_double2(1e20, 1e20);
+    t.z[TileXYOf<CAP>::kDummy] = 1e20;
+  }
+  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+    const int lo = t.cell[u];
+    const int src = t.src[lo] + (u - t.prefix[lo]);
+    const int code = t.code[lo];
+    t.xy[u] = make_double2(x[src] + (double)((code & 3) - 1) * g.box[0],
+                           y[src] + (double)(((code >> 2) & 3) - 1) * g.box[1]);
+    t.z[u] = z[src] + (double)(((code >> 4) & 3) - 1) * g.box[2];
   }
   __syncthreads();
 }
