@@ -156,7 +156,7 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
     for (int gi = 0; gi < ng; ++gi) {
       const uint64_t word = col[(int64_t)gi * tl.stride];
       for (int q = 0; q < 4; ++q) {
-        const int u = (int)((word >> (16 * q)) & 0xffff) >> 3;
+        const int u = (int)((word >> (16 * q)) & 0xffff) >> kFullShift;
         const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (!(d2 < rc2)) continue;
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
     for (int gi = part; gi < ng; gi += 2) {
       const uint64_t word = col[(int64_t)gi * tl.stride];
       for (int q = 0; q < 4; ++q) {
-        const int u = (int)((word >> (16 * q)) & 0xffff) >> 3;
+        const int u = (int)((word >> (16 * q)) & 0xffff) >> kFullShift;
         if (u >= nt) continue;  // padding slot
         const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;

@@ -124,6 +124,11 @@ constexpr int kTileDummy = kTileMax - 1;    // padding slot
 constexpr int kTileCap = kTileMax - 1;      // particles a tile can hold
 constexpr int kTileCells = 125;             // B <= 3 per axis
 constexpr int kTileMaxHalf = 2144;          // tile slots of a half-list tile (LDS)
+// A list entry is the partner's tile slot u as a byte offset: u << 4 in full
+// lists (the plain force pass reads the 16-byte x-y pair there and z at half
+// of it), u << 3 in half lists (8-byte arrays).
+constexpr int kFullShift = 4;
+constexpr int kHalfShift = 3;
 struct TileList {
   uint64_t* nbr;
   int32_t* cnt;     // clamped to max_nb

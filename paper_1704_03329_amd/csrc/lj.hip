@@ -108,16 +108,19 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
       constexpr bool kAhead = !ENERGY && sizeof(MT) == 4;
       double qx, qy, qz;
       auto tile_pos = [&](int k) {
-        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;  // byte offset in t.z
+        // entry: the slot's byte offset in the 16-byte x-y pairs; half of it
+        // in the 8-byte arrays
+        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;
+        const unsigned off8 = (unsigned)(word >> (16 * k + 1)) & 0x7fffu;
         if constexpr (ENERGY) {
-          qx = *(const double*)((const char*)t.x + off);
-          qy = *(const double*)((const char*)t.y + off);
+          qx = *(const double*)((const char*)t.x + off8);
+          qy = *(const double*)((const char*)t.y + off8);
         } else {
-          const double2 q = *(const double2*)((const char*)t.xy + 2 * off);
+          const double2 q = *(const double2*)((const char*)t.xy + off);
           qx = q.x;
           qy = q.y;
         }
-        qz = *(const double*)((const char*)t.z + off);
+        qz = *(const double*)((const char*)t.z + off8);
       };
       tile_pos(0);
 #pragma unroll

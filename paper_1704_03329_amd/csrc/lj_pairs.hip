@@ -85,7 +85,7 @@ void k_lj_force_half(const double* __restrict__ x, const double* __restrict__ y,
       if (gi + LPP < ngroups) next = col[(int64_t)(gi + LPP) * tl.stride];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int u = (int)((word >> (16 * k)) & 0xffffu) >> 3;  // tile slot of j
+        const int u = (int)((word >> (16 * k)) & 0xffffu) >> kHalfShift;  // tile slot of j
         const double dx = xi - t.x[u], dy = yi - t.y[u], dz = zi - t.z[u];
         double gd;
         bool in;

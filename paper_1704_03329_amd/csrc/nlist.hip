@@ -11,7 +11,7 @@
 // Two builders:
 //  * the LJ list: one workgroup per brick stages its tile (stored positions,
 //    no images) in LDS, one wave per home cell tests the 27 tile cells of its
-//    stencil; entries are 16-bit tile byte offsets, column-major, so the force
+//    stencil; entries are 16-bit tile byte offsets (16 x slot), column-major, so the force
 //    pass reads one coalesced word per four neighbours.  A half list (each
 //    pair once, Newton's third law) keeps j in the list of i only if j's tile
 //    index is larger (tile.h): four of the nine stencil rows whole, and the
@@ -67,7 +67,7 @@ struct RowScan {
 // end read the far-away dummy.  One LDS atomic reserves the ranks of all
 // accepted candidates of a step; each candidate's offset among them is
 // known before it, so a store needs one comparison with the capacity.
-template <int UNROLL, typename TS>
+template <int UNROLL, int SHIFT, typename TS>
 __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const RowScan& q) {
   for (int u0 = ub; u0 < ue; u0 += UNROLL * q.K) {
     constexpr uint32_t kNone = 1u << 20;  // offset of a rejected candidate: past any list
@@ -101,7 +101,7 @@ __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const Ro
       for (int j = 0; j < UNROLL; ++j) {
         const uint32_t mj = m + rank[j];
         if (mj < (uint32_t)q.max_nb)
-          q.base[(uint64_t)(mj >> 2) * q.stride4 + (mj & 3u)] = (uint16_t)(uu[j] << 3);
+          q.base[(uint64_t)(mj >> 2) * q.stride4 + (mj & 3u)] = (uint16_t)(uu[j] << SHIFT);
       }
     }
   }
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           if (HALF && ub <= self) ub = self + 1;
           int ue = t.prefix[tcl + 3];
           ue = ue < TS::kCap ? ue : TS::kCap;
-          scan_range<4>(t, ub + k, ue, q);
+          scan_range<4, HALF ? kHalfShift : kFullShift>(t, ub + k, ue, q);
         }
       }
     }
@@ -223,7 +223,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const int count = la < kBrickMax ? acnt[la] : 0;
     const int kept = count < max_nb ? count : max_nb;
     for (int m = kept; m < ((kept + 3) & ~3); ++m)  // pad the last word
-      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] = (uint16_t)(TS::kDummy << 3);
+      half[((int64_t)(m >> 2) * tl.stride + s) * 4 + (m & 3)] =
+          (uint16_t)(TS::kDummy << (HALF ? kHalfShift : kFullShift));
     tl.cnt[s] = kept;
     if (count > max_nb) atomicOr(flags, MDPL_FLAG_NL_OVERFLOW);
     most = count > most ? count : most;
@@ -279,7 +280,8 @@ __global__ __launch_bounds__(1024) void k_export_tile_pairs(
     const int32_t pi = perm[s];
     for (int m = 0; m < c; ++m) {
       if (o + m >= cap) break;
-      const int u = (int)((tl.nbr[(int64_t)(m >> 2) * tl.stride + s] >> (16 * (m & 3))) & 0xffff) >> 3;
+      const int u = (int)((tl.nbr[(int64_t)(m >> 2) * tl.stride + s] >> (16 * (m & 3))) & 0xffff) >>
+                    (tl.half ? kHalfShift : kFullShift);
       const int lo = tile_cell_of(t, ntc, u);
       i_out[o + m] = pi;
       j_out[o + m] = perm[t.src[lo] + (u - t.prefix[lo])];

@@ -43,7 +43,7 @@ struct TileOf {
 };
 static_assert(kTileCells <= 256, "a tile cell index must fit the byte map");
 // full-list force pass: x and y of a slot side by side (one 16-byte read),
-// z apart; list entries stay byte offsets into the 8-byte z array
+// z apart; a full-list entry is the byte offset of the slot's x-y pair
 template <int CAP>
 struct TileXYOf {
   static constexpr int kSlots = CAP;
