@@ -218,7 +218,7 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
                          void* fx, void* fy, void* fz, const int32_t* scatter, bool energy,
                          double* e_atom, double* pe_w_dst, int kind, int timing_slot,
                          const StateArrays* kick = nullptr, double* const* spare = nullptr,
-                         double* ke_dst = nullptr) {
+                         double* ke_dst = nullptr, double* disp_dst = nullptr) {
   ForceOut out;
   out.fx = fx;
   out.fy = fy;
@@ -251,10 +251,25 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
     s->tm.ev[timing_slot].push_back(e0);
     s->tm.ev[timing_slot].push_back(e1);
   }
-  const int stride = out.fuse ? 3 : 2;
-  if (energy && pe_w_dst) HIP_TRY(reduce_partials(s->partials, nb, stride, 2, pe_w_dst, 1.0, s->st));
-  if (out.fuse && energy && ke_dst)
-    HIP_TRY(reduce_partials(s->partials + 2, nb, 3, 1, ke_dst, 0.5 * s->p.mass, s->st));
+  // PE, W (and the fused KE) of a sampled step, and the row's maximum
+  // displacement (disp_dst), in one launch
+  if (energy && pe_w_dst) {
+    RowOut o{};
+    o.dst[0] = pe_w_dst;
+    o.dst[1] = pe_w_dst + 1;
+    o.scale[0] = o.scale[1] = 1.0;
+    int ncomp = 2;
+    if (out.fuse && ke_dst) {
+      o.dst[2] = ke_dst;
+      o.scale[2] = 0.5 * s->p.mass;
+      ncomp = 3;
+    }
+    if (disp_dst) {
+      o.csrc = s->max_disp;
+      o.cdst = disp_dst;
+    }
+    HIP_TRY(reduce_row(s->partials, nb, out.fuse ? 3 : 2, ncomp, o, s->st));
+  }
   return MDPL_OK;
 }
 
@@ -497,8 +512,10 @@ mdpl_status mdpl_kernel_time(mdpl_sim* s, int32_t which, double* ms, int64_t* la
 namespace {
 
 // The time loop of Alg. VelocityVerlet with list reuse (Sec. 3.5), shared by
-// the LJ and learned-potential runs.  force(cur, energy, pe_w_dst, slot)
-// fills cur.f* from cur positions (and PE, W into pe_w_dst on sampled steps).
+// the LJ and learned-potential runs.  force(cur, energy, pe_w_dst, slot, fuse,
+// spare, ke_dst, disp_dst) fills cur.f* from cur positions (on sampled steps
+// also PE, W into pe_w_dst and the maximum displacement since the last build
+// into disp_dst).
 // th (nullable): Andersen collisions after every completed step; global
 // step numbers start at th->step (the step0 of mdpl_run_andersen) + 1.
 template <typename ForceFn>
@@ -543,14 +560,14 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
 
   mdpl_status r = rebuild();
   if (r != MDPL_OK) return r;
-  r = force(cur, sampled(0), sampled(0) ? row(0) + 1 : nullptr, -1, false, spare, nullptr);
+  r = force(cur, sampled(0), sampled(0) ? row(0) + 1 : nullptr, -1, false, spare, nullptr,
+            sampled(0) ? row(0) + 3 : nullptr);
   if (r != MDPL_OK) return r;
   if (sampled(0)) {
     int nb = 0;
     HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
                     h, dt, 3, true, s->partials, s->flags, s->st, &nb));
     HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(0), ke_scale, s->st));
-    HIP_TRY(hipMemcpyAsync(row(0) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
   }
   // the collisions at the end of global step g (the kick completing it is in vv_step)
   auto collide = [&](int64_t local) -> const Andersen* {
@@ -578,7 +595,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     // the pass of the last step stores its forces for the final half kick
     fused = can_fuse && step < nsteps;
     r = force(cur, en, en ? row(step) + 1 : nullptr, en ? 1 : 0, fused, spare,
-              en ? row(step) : nullptr);
+              en ? row(step) : nullptr, en ? row(step) + 3 : nullptr);
     if (r != MDPL_OK) return r;
     if (fused) {
       double* t[3] = {cur.x, cur.y, cur.z};
@@ -589,7 +606,6 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
       spare[1] = t[1];
       spare[2] = t[2];
     }
-    if (en) HIP_TRY(hipMemcpyAsync(row(step) + 3, s->max_disp, 8, hipMemcpyDeviceToDevice, s->st));
   }
   if (nsteps > 0) {
     const bool ke = sampled(nsteps);
@@ -640,10 +656,10 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
   // complete only when its pass has ended; the cell pass has no fused form)
   return run_loop(s, user, nsteps, sample_every, thermo, !s->tl.half && !s->tl.cells,
                   [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool fuse,
-                      double* const* spare, double* ke) {
+                      double* const* spare, double* ke, double* disp) {
                     return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr,
                                         en, nullptr, pe_w, prec, slot, fuse ? &cur : nullptr,
-                                        spare, ke);
+                                        spare, ke, disp);
                   });
 }
 
@@ -663,9 +679,10 @@ mdpl_status mdpl_run_andersen(mdpl_sim* s, double* x, double* y, double* z, doub
   // the collisions sit between the kicks of vv_step: no fused kicks
   return run_loop(
       s, user, nsteps, sample_every, thermo, false,
-      [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool, double* const*, double*) {
+      [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool, double* const*, double*,
+          double* disp) {
         return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr, en, nullptr,
-                            pe_w, prec, slot);
+                            pe_w, prec, slot, nullptr, nullptr, nullptr, disp);
       },
       &th);
 }
@@ -885,7 +902,7 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
   StateArrays user{x, y, z, vx, vy, vz, fx, fy, fz, ids};
   return run_loop(s, user, nsteps, sample_every, thermo, false,
                   [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool,
-                      double* const*, double*) -> mdpl_status {
+                      double* const*, double*, double* disp) -> mdpl_status {
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (s->timing && slot >= 0) {
                       HIP_TRY(hipEventCreate(&e0));
@@ -906,11 +923,18 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
                       s->tm.ev[slot].push_back(e0);
                       s->tm.ev[slot].push_back(e1);
                     }
-                    if (en && pe_w) {
+                    if (en && pe_w) {  // PE; no virial (zero); the maximum displacement
                       int nb = 0;
                       HIP_TRY(sum_f32(e, n, s->partials, s->st, &nb));
-                      HIP_TRY(reduce_partials(s->partials, nb, 1, 1, pe_w, 1.0, s->st));
-                      HIP_TRY(hipMemsetAsync(pe_w + 1, 0, 8, s->st));
+                      RowOut o{};
+                      o.dst[0] = pe_w;
+                      o.scale[0] = 1.0;
+                      o.zdst = pe_w + 1;
+                      if (disp) {
+                        o.csrc = s->max_disp;
+                        o.cdst = disp;
+                      }
+                      HIP_TRY(reduce_row(s->partials, nb, 1, 1, o, s->st));
                     }
                     return MDPL_OK;
                   });

@@ -356,7 +356,6 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
     acc[2][u] = 0.0f;
   }
   tile_load<true>(g, x, y, z, total, t);  // ends with a barrier
-  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const double rc2 = (double)rc * (double)rc;
   const float pi_rc = 3.14159265358979f / rc;
@@ -399,12 +398,7 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
   }
   __syncthreads();
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
-    int lo = 0, hi = ntc;  // tile cell of u
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (t.prefix[mid] <= u) lo = mid;
-      else hi = mid;
-    }
+    const int lo = t.cell[u];  // tile cell of u (slot map filled by tile_load)
     const int sj = t.src[lo] + (u - t.prefix[lo]);
     const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
     const float ax = acc[0][u], ay = acc[1][u], az = acc[2][u];

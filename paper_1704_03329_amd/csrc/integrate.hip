@@ -145,6 +145,31 @@ hipError_t reduce_partials(const double* partials, int nblocks, int stride, int 
   return hipGetLastError();
 }
 
+// A thermo row in one launch: component c of the partials (the same fixed
+// order as k_reduce_partials) times o.scale[c] to o.dst[c] (skipped if
+// null), then the optional 8-byte copy and zero.
+__global__ __launch_bounds__(256) void k_reduce_row(const double* __restrict__ p, int nb,
+                                                    int stride, int ncomp, RowOut o) {
+  __shared__ double sh[4];
+  for (int comp = 0; comp < ncomp; ++comp) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) v += p[(int64_t)k * stride + comp];
+    const double t = block_sum256(v, sh);
+    if (threadIdx.x == 0 && o.dst[comp]) *o.dst[comp] = o.scale[comp] * t;
+  }
+  if (threadIdx.x == 0) {
+    if (o.cdst) *o.cdst = *o.csrc;
+    if (o.zdst) *o.zdst = 0.0;
+  }
+}
+
+hipError_t reduce_row(const double* partials, int nblocks, int stride, int ncomp, const RowOut& o,
+                      hipStream_t st) {
+  if (ncomp < 0 || ncomp > 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_row, dim3(1), dim3(256), 0, st, partials, nblocks, stride, ncomp, o);
+  return hipGetLastError();
+}
+
 }  // namespace mdpl
 
 namespace mdpl {

@@ -206,6 +206,20 @@ hipError_t vv_step(double* x, double* y, double* z, double* vx, double* vy, doub
 hipError_t reduce_partials(const double* partials, int nblocks, int stride, int ncomp,
                            double* out, double scale, hipStream_t st);
 
+// Destinations of reduce_row: dst[c] = scale[c] * (sum of component c), each
+// skipped if null; then *cdst = *csrc and *zdst = 0 where given.
+struct RowOut {
+  double* dst[3];
+  double scale[3];
+  const double* csrc;
+  double* cdst;
+  double* zdst;
+};
+// Up to three components (the sums of reduce_partials, same order) and the
+// copy/zero of RowOut in one launch.
+hipError_t reduce_row(const double* partials, int nblocks, int stride, int ncomp, const RowOut& o,
+                      hipStream_t st);
+
 // Per-block maxima of |r - r_build|^2 into partials.
 hipError_t disp_partials(const double* x, const double* y, const double* z, const double* xb,
                          const double* yb, const double* zb, int64_t n, double* partials,
