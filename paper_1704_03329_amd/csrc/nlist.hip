@@ -60,6 +60,7 @@ struct RowScan {
   int* cnt;                    // the particle's LDS counter
   uint16_t* base;              // its list: entry m at base[(m >> 2) * stride4 + (m & 3)]
   uint32_t stride4;
+  uint32_t pitch;              // bytes per word row, 2 * stride4
 };
 
 // Candidates u = ub, ub + K, ... < ue (one contiguous range of tile
@@ -67,7 +68,9 @@ struct RowScan {
 // end read the far-away dummy.  One LDS atomic reserves the ranks of all
 // accepted candidates of a step; each candidate's offset among them is
 // known before it, so a store needs one comparison with the capacity.
-template <int UNROLL, int SHIFT, typename TS>
+// A24: the word-row pitch is below 2^24 bytes, so the byte offset of rank m
+// (below 2^32, as m >> 2 < 2^8) comes from a 24-bit product.
+template <int UNROLL, int SHIFT, bool A24, typename TS>
 __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const RowScan& q) {
   for (int u0 = ub; u0 < ue; u0 += UNROLL * q.K) {
     constexpr uint32_t kNone = 1u << 20;  // offset of a rejected candidate: past any list
@@ -100,8 +103,13 @@ __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const Ro
 #pragma unroll
       for (int j = 0; j < UNROLL; ++j) {
         const uint32_t mj = m + rank[j];
-        if (mj < (uint32_t)q.max_nb)
-          q.base[(uint64_t)(mj >> 2) * q.stride4 + (mj & 3u)] = (uint16_t)(uu[j] << SHIFT);
+        if (mj < (uint32_t)q.max_nb) {
+          if constexpr (A24)
+            *(uint16_t*)((char*)q.base + (__umul24(mj >> 2, q.pitch) + ((mj & 3u) << 1))) =
+                (uint16_t)(uu[j] << SHIFT);
+          else
+            q.base[(uint64_t)(mj >> 2) * q.stride4 + (mj & 3u)] = (uint16_t)(uu[j] << SHIFT);
+        }
       }
     }
   }
@@ -109,7 +117,7 @@ __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const Ro
 
 // One wave per home cell (up to 16 per workgroup); at most 64 VGPRs so that
 // two 1024-thread workgroups share a CU.  TS: the tile (full or half list).
-template <typename TS, bool HALF>
+template <typename TS, bool HALF, bool A24>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_build_tile_nlist(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ skeys, const int32_t* __restrict__ cs, Grid g, double r2,
@@ -199,6 +207,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       q.cnt = &acnt[ok ? la : 0];
       q.base = half + (int64_t)(ok ? s : 0) * 4;
       q.stride4 = (uint32_t)(tl.stride * 4);
+      q.pitch = (uint32_t)(tl.stride * 8);
       for (int oz = -1; oz <= 1; ++oz) {
         for (int oy2 = -1; oy2 <= 1; ++oy2) {
           // a stencil row: three consecutive tile cells, one contiguous index range
@@ -210,7 +219,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           if (HALF && ub <= self) ub = self + 1;
           int ue = t.prefix[tcl + 3];
           ue = ue < TS::kCap ? ue : TS::kCap;
-          scan_range<4, HALF ? kHalfShift : kFullShift>(t, ub + k, ue, q);
+          scan_range<4, HALF ? kHalfShift : kFullShift, A24>(t, ub + k, ue, q);
         }
       }
     }
@@ -254,11 +263,14 @@ hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
   const float guard = (float)(8.0 * err);
   const dim3 grid(tile_grid(g));
   if (tl.half)
-    hipLaunchKernelGGL((k_build_tile_nlist<TileHalf32, true>), grid, dim3(threads), 0, st, x, y, z,
-                       skeys, cell_start, g, r2, guard, tl, flags, maxcount);
+    hipLaunchKernelGGL((k_build_tile_nlist<TileHalf32, true, false>), grid, dim3(threads), 0, st,
+                       x, y, z, skeys, cell_start, g, r2, guard, tl, flags, maxcount);
+  else if (tl.stride * 8 < (int64_t)(1 << 24))
+    hipLaunchKernelGGL((k_build_tile_nlist<TileShared32, false, true>), grid, dim3(threads), 0, st,
+                       x, y, z, skeys, cell_start, g, r2, guard, tl, flags, maxcount);
   else
-    hipLaunchKernelGGL((k_build_tile_nlist<TileShared32, false>), grid, dim3(threads), 0, st, x, y,
-                       z, skeys, cell_start, g, r2, guard, tl, flags, maxcount);
+    hipLaunchKernelGGL((k_build_tile_nlist<TileShared32, false, false>), grid, dim3(threads), 0,
+                       st, x, y, z, skeys, cell_start, g, r2, guard, tl, flags, maxcount);
   return hipGetLastError();
 }
 
