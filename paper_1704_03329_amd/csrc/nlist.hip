@@ -70,28 +70,34 @@ struct RowScan {
 // known before it, so a store needs one comparison with the capacity.
 // A24: the word-row pitch is below 2^24 bytes, so the byte offset of rank m
 // (below 2^32, as m >> 2 < 2^8) comes from a 24-bit product.
+// Candidate indices are carried as byte offsets into the 4-byte tile
+// arrays (4 u), which saves a shift per candidate.
 template <int UNROLL, int SHIFT, bool A24, typename TS>
 __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const RowScan& q) {
-  for (int u0 = ub; u0 < ue; u0 += UNROLL * q.K) {
+  const int ue4 = 4 * ue, step4 = 4 * UNROLL * q.K, k4 = 4 * q.K, self4 = 4 * q.self;
+  for (int u04 = 4 * ub; u04 < ue4; u04 += step4) {
     constexpr uint32_t kNone = 1u << 20;  // offset of a rejected candidate: past any list
-    int uu[UNROLL];
+    int uu4[UNROLL];
     uint32_t rank[UNROLL];  // offset among this step's accepted candidates, or kNone
     uint32_t na = 0;
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
-      const int u = u0 + j * q.K;
-      uu[j] = u < ue ? u : TS::kDummy;
+      const int u4 = u04 + j * k4;
+      uu4[j] = u4 < ue4 ? u4 : 4 * TS::kDummy;
     }
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
-      const float dx = q.xi - t.x[uu[j]], dy = q.yi - t.y[uu[j]], dz = q.zi - t.z[uu[j]];
+      const float dx = q.xi - *(const float*)((const char*)t.x + uu4[j]);
+      const float dy = q.yi - *(const float*)((const char*)t.y + uu4[j]);
+      const float dz = q.zi - *(const float*)((const char*)t.z + uu4[j]);
       const float d2f = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-      const bool other = uu[j] != q.self;
+      const bool other = uu4[j] != self4;
       bool acc = other && d2f < q.r2lo;
       if (other && !(d2f < q.r2lo) && d2f <= q.r2hi) {
         // inside the guard band: the definition decides
-        const int c = t.cell[uu[j]];
-        const int sj = t.src[c] + (uu[j] - t.prefix[c]);
+        const int u = uu4[j] >> 2;
+        const int c = t.cell[u];
+        const int sj = t.src[c] + (u - t.prefix[c]);
         acc = exact_d2(q.xs, q.ys, q.zs, q.x[sj], q.y[sj], q.z[sj], q.Lx, q.Ly, q.Lz, q.hx, q.hy,
                        q.hz) < q.r2;
       }
@@ -106,9 +112,9 @@ __device__ __forceinline__ void scan_range(const TS& t, int ub, int ue, const Ro
         if (mj < (uint32_t)q.max_nb) {
           if constexpr (A24)
             *(uint16_t*)((char*)q.base + (__umul24(mj >> 2, q.pitch) + ((mj & 3u) << 1))) =
-                (uint16_t)(uu[j] << SHIFT);
+                (uint16_t)(uu4[j] << (SHIFT - 2));
           else
-            q.base[(uint64_t)(mj >> 2) * q.stride4 + (mj & 3u)] = (uint16_t)(uu[j] << SHIFT);
+            q.base[(uint64_t)(mj >> 2) * q.stride4 + (mj & 3u)] = (uint16_t)(uu4[j] << (SHIFT - 2));
         }
       }
     }
