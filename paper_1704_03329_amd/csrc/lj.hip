@@ -89,9 +89,11 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
   const int part = (int)threadIdx.x % LPP;
   for (int s = s0 + (int)threadIdx.x / LPP; s < s1; s += (int)blockDim.x / LPP) {
     const double xi = x[s], yi = y[s], zi = z[s];
-    // velocities for the fused kick, loaded early so the pair loop hides the latency
+    // velocities for the fused kick: the plain pass loads them early so that
+    // the pair loop hides the latency; the energy pass, short of registers,
+    // after the loop
     double vxi = 0.0, vyi = 0.0, vzi = 0.0;
-    if (out.fuse && part == 0) {
+    if (!ENERGY && out.fuse && part == 0) {
       vxi = out.vx[s];
       vyi = out.vy[s];
       vzi = out.vz[s];
@@ -172,6 +174,11 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
       if (part) continue;
     }
     if (out.fuse) {
+      if (ENERGY) {
+        vxi = out.vx[s];
+        vyi = out.vy[s];
+        vzi = out.vz[s];
+      }
       // the kicks use the force as stored (rounded to OT), like k_vv
       ke += fused_kick(out, s, xi, yi, zi, vxi, vyi, vzi, (double)(OT)(ax * scale),
                        (double)(OT)(ay * scale), (double)(OT)(az * scale));
