@@ -99,10 +99,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const int32_t* __re
   hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
 }
 
+// offs: the histogram scanned within blocks of 1024 counters, sums: the
+// exclusive prefix of those blocks (the two halves of an exclusive scan).
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int32_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
-    int ntiles, const int32_t* __restrict__ offs, int32_t* __restrict__ kout,
-    int32_t* __restrict__ vout) {
+    int ntiles, const int32_t* __restrict__ offs, const int32_t* __restrict__ sums,
+    int32_t* __restrict__ kout, int32_t* __restrict__ vout) {
   constexpr int kWaves = kSortThreads / 64;
   __shared__ int run[kRadixBins];
   __shared__ int wc[kWaves][kRadixBins];
@@ -110,7 +112,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  run[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+  const int64_t hi = (int64_t)tid * ntiles + blockIdx.x;
+  run[tid] = offs[hi] + sums[hi >> 10];
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int r = 0; r < kSortItems; ++r) {
 #pragma unroll
@@ -254,10 +257,14 @@ hipError_t bin_particles(const double* x, const double* y, const double* z, int6
     const int shift = p * kRadixBits;
     hipLaunchKernelGGL(k_radix_hist, dim3(s.ntiles), dim3(kSortThreads), 0, st, s.keys[cur], n,
                        shift, s.ntiles, s.hist);
-    hipError_t e = exclusive_scan(s.hist, s.hist, hn, s.blocksums, false, st);
-    if (e != hipSuccess) return e;
+    // the scan's final add is left to the scatter (one launch fewer per pass)
+    const int64_t nsb = div_up(hn, 1024);
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, st, s.hist, s.hist, hn,
+                       s.blocksums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, s.blocksums, nsb);
     hipLaunchKernelGGL(k_radix_scatter, dim3(s.ntiles), dim3(kSortThreads), 0, st, s.keys[cur],
-                       s.vals[cur], n, shift, s.ntiles, s.hist, s.keys[cur ^ 1], s.vals[cur ^ 1]);
+                       s.vals[cur], n, shift, s.ntiles, s.hist, s.blocksums, s.keys[cur ^ 1],
+                       s.vals[cur ^ 1]);
     cur ^= 1;
   }
   hipLaunchKernelGGL(k_cell_start, dim3(nb), dim3(256), 0, st, s.keys[cur], n, g.nkeys,
