@@ -5,8 +5,10 @@
 // written once per particle (gather only, no atomics: the paper's choice of
 // looping over all ordered pairs and writing to the first particle, Sec. 2).
 // Each workgroup handles one brick of cells and stages the image positions of
-// its neighbourhood in LDS (tile.h); list entries are byte offsets into the
-// tile.  The cutoff test d2 < rc^2 uses the FP64 separation; the periodic
+// its neighbourhood in LDS (tile.h): the plain pass keeps x and y of a slot
+// side by side and z apart, the energy pass three arrays.  A list entry is 16
+// times the partner's slot, the byte offset of its x-y pair; half of it
+// indexes the 8-byte arrays.  The cutoff test d2 < rc^2 uses the FP64 separation; the periodic
 // image is added to a tile position once, and the plain pass forms d2 with
 // fused multiply-adds, so a pair can be classified differently from the
 // definition only within a few units in the last place of rc^2.  The
