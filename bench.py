@@ -469,6 +469,16 @@ def main():
             "launches": f_n,
         },
         "flops": flops,
+        # context only, another machine and precision: the paper's framework on
+        # its N=10^6 LJ benchmark (FP64, skin 0.25, list rebuilt every 20
+        # steps), 10^4 steps in 385 s on one GPU and 501 s on one CPU node
+        # (Sec. 5.1, Tab. strong_table); atom-steps/s = N x steps / time
+        "paper_context": [
+            {"value": 1e6 * 1e4 / 385.0, "unit": "atom-steps/s", "hardware": "1x NVIDIA Tesla K20X",
+             "dtype": "f64"},
+            {"value": 1e6 * 1e4 / 501.0, "unit": "atom-steps/s",
+             "hardware": "2x Intel Xeon E5-2650v2 (16 cores)", "dtype": "f64"},
+        ],
         "kernels_us": {
             "force": avg_s * 1e6,
             "force_energy_virial": (fe_ms / max(fe_n, 1)) * 1e3,
