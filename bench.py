@@ -254,16 +254,22 @@ def analysis_report():
     n = x.numel()
     dev = x.device
     ws_b = torch.empty(C.mdpl_analysis_workspace_bytes(n, box, rc, 1), dtype=torch.uint8, device=dev)
-    ws_c = torch.empty(C.mdpl_analysis_workspace_bytes(n, box, rc, 16), dtype=torch.uint8, device=dev)
+    # CNA bond-list capacity: triplets are computed for every particle with at
+    # most this many bonds (labels are exact at any capacity >= 14)
+    cap = 32
+    ws_c = torch.empty(C.mdpl_analysis_workspace_bytes(n, box, rc, cap), dtype=torch.uint8, device=dev)
     q4 = torch.empty(n, dtype=torch.float32, device=dev)
     q6 = torch.empty_like(q4)
     nnb = torch.empty(n, dtype=torch.int32, device=dev)
-    trip = torch.empty((n, 16), dtype=torch.int32, device=dev)
+    trip = torch.empty((n, cap), dtype=torch.int32, device=dev)
     label = torch.empty(n, dtype=torch.uint8, device=dev)
+    most = torch.zeros(1, dtype=torch.int32, device=dev)
     t_boa = event_time(lambda: C.mdpl_boa(x, y, z, box, rc, q4, None, q6, nnb, ws_b), 5)
-    t_cna = event_time(lambda: C.mdpl_cna(x, y, z, box, rc, 16, trip, nnb, label, ws_c), 5)
+    t_cna = event_time(lambda: C.mdpl_cna(x, y, z, box, rc, cap, trip, nnb, label, ws_c, most), 5)
     frac = np.bincount(label.cpu().numpy(), minlength=4) / n
-    log(f"analysis: BOA {t_boa * 1e3:.2f} ms, CNA {t_cna * 1e3:.2f} ms")
+    max_bonds = int(most.item())
+    log(f"analysis: BOA {t_boa * 1e3:.2f} ms, CNA {t_cna * 1e3:.2f} ms (capacity {cap}, "
+        f"largest bond count {max_bonds})")
     return {
         "workload": f"50 FCC/HCP/BCC grains, N={n}, rho 1.0, jitter 0.05 d, seed 3, cutoff {rc:.4f} "
                     "(neighbour list, bond order and CNA each included)",
@@ -273,6 +279,9 @@ def analysis_report():
         "boa_atoms_per_s": n / t_boa,
         "cna_atoms_per_s": n / t_cna,
         "label_fractions": {k: float(v) for k, v in zip(("other", "fcc", "hcp", "bcc"), frac)},
+        "cna_capacity": cap,
+        "max_bond_count": max_bonds,
+        "cna_all_triplets_computed": max_bonds <= cap,
     }
 
 
@@ -377,20 +386,25 @@ def main():
         state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
         torch.cuda.synchronize()
         log(f"pairs={pairs}: warmup {warmup} steps")
-        sim.run(state, warmup, 10)
+        # the warmup samples its last step, so that the timed run, which goes
+        # on from its state (list, forces, rebuild schedule), starts from its row
+        sim.run(state, warmup, max(warmup, 1))
         torch.cuda.synchronize()
         st, flags, _ = sim.check(raise_on_error=False)
         if st != 0:
             raise SystemExit(f"warmup flagged status {st} flags {flags}")
-        C.mdpl_set_timing(sim.handle, True)
+        # events for every launch of the timed run are created here, not in it
+        C.mdpl_set_timing(sim.handle, True, reserve=steps + 8)
         C.mdpl_kernel_time(sim.handle, 0)  # reset
         C.mdpl_kernel_time(sim.handle, 1)
+        rb0 = sim.rebuild_stats()
         log(f"timing {steps} steps")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        thermo = sim.run(state, steps, 10)
+        thermo = sim.run(state, steps, 10, cont=warmup > 0)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        rb = [a - b for a, b in zip(sim.rebuild_stats(), rb0)]
         st, flags, _ = sim.check(raise_on_error=False)
         if st != 0:
             raise SystemExit(f"timed run flagged status {st} flags {flags}")
@@ -399,9 +413,10 @@ def main():
         C.mdpl_set_timing(sim.handle, False)
         entries = C.mdpl_nlist_entries(sim.handle) if pairs != "cells" else 0
         log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
-            f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}")
+            f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}; "
+            f"rebuilds {rb[0]} (early {rb[1]}, host waits {rb[2]})")
         return dict(elapsed=elapsed, thermo=thermo.cpu().numpy(), f_ms=f_ms, f_n=f_n, fe_ms=fe_ms, fe_n=fe_n,
-                    entries=entries)
+                    entries=entries, rebuilds=rb)
 
     r = timed_run(args.pairs, args.warmup, args.steps)
     elapsed, th, entries = r["elapsed"], r["thermo"], r["entries"]
@@ -483,6 +498,9 @@ def main():
             "force": avg_s * 1e6,
             "force_energy_virial": (fe_ms / max(fe_n, 1)) * 1e3,
         },
+        "rebuilds": {"total": r["rebuilds"][0], "early_by_vmax_rule": r["rebuilds"][1],
+                     "host_waits": r["rebuilds"][2],
+                     "rule": "every 10 steps, or earlier once 2 sum dt v_max >= skin (Eq. extended_cutoff)"},
         "energy_drift_per_atom": float(np.max(np.abs(etot - etot[0])) / n),
         "hbm_gbs_force": achieved,
     }

@@ -89,6 +89,39 @@ typedef int32_t mdpl_status;
 #define MDPL_PAIRS_HALF 1
 #define MDPL_PAIRS_CELLS 2
 
+/* When the runs rebuild the cell and neighbour lists (Sec. 3.5, Eq.
+ * extended_cutoff and the IntegratorRange paragraph, which takes the time
+ * step, the velocities, a largest reuse count and the shell thickness).
+ * FIXED: every reuse_every steps.
+ * VMAX:  every reuse_every steps, and also as soon as
+ *        2 * sum over the steps since the last build of dt * max_i |v_i| >= skin,
+ *        the condition of Eq. extended_cutoff under which no pair inside rc
+ *        can be missing from the list.  The largest speed of every step is
+ *        found on the device by the kernel that moves the particles; the host
+ *        waits for the stream only when a prediction from the speeds it has
+ *        already seen (allowed to double) says the threshold may be reached,
+ *        and then decides on the exact value.  Each context holds
+ *        64 x 32 bytes of pinned host memory for these records.
+ * In both modes every rebuild checks the displacement of the last positions
+ * used with the old list against skin/2 (MDPL_FLAG_SKIN). */
+#define MDPL_REBUILD_FIXED 0
+#define MDPL_REBUILD_VMAX 1
+
+/* How a run starts.
+ * SETUP:    bin the particles, build the list and compute F(r0) (and the
+ *           energy of step 0 if sampled).
+ * CONTINUE: take over the state that the last run of the same force field
+ *           (LJ, with or without thermostat, or learned) on this context left
+ *           in the SAME arrays: its list, its forces (no F(r0) pass) and its
+ *           count of steps since the last build (the rebuild schedule goes
+ *           on).  The caller must not have changed positions, forces or ids
+ *           since; velocities may have been changed (e.g. rescaled).  With
+ *           unchanged velocities the result is bit-identical to one longer
+ *           run.  MDPL_ESTATE if there is no such state (other arrays,
+ *           another force field, an mdpl_build since). */
+#define MDPL_RUN_SETUP 0
+#define MDPL_RUN_CONTINUE 1
+
 typedef struct {
   int64_t n;          /* number of particles, 1 .. 2^26 */
   double box[3];      /* periodic box [0,Lx) x [0,Ly) x [0,Lz) */
@@ -102,6 +135,7 @@ typedef struct {
   int32_t precision;  /* MDPL_FP64 or MDPL_FP32 */
   int32_t max_nb;     /* neighbour-list capacity per particle (1 .. 1024) */
   int32_t pairs;      /* MDPL_PAIRS_*: how the pair loop finds the pairs within rc */
+  int32_t rebuild;    /* MDPL_REBUILD_*: when the runs rebuild the lists */
 } mdpl_lj_params;
 
 typedef struct mdpl_sim mdpl_sim;
@@ -162,22 +196,26 @@ mdpl_status mdpl_lj_backward(mdpl_sim* sim, const double* x, const double* y, co
 
 /* Integrate nsteps of velocity Verlet (Alg. VelocityVerlet): F(r0) first,
  * then per step v += dt/(2m) F; r += dt v; F = forces(r); v += dt/(2m) F.
- * The cell and neighbour lists are rebuilt at the start and after every
- * reuse_every-th step.  At every rebuild the particles are reordered by cell
- * IN PLACE in all ten arrays (positions folded into [0, L)), so that
+ * The cell and neighbour lists are rebuilt at the start (start =
+ * MDPL_RUN_SETUP) and then as mdpl_lj_params.rebuild says; with
+ * MDPL_RUN_CONTINUE the run goes on from the previous run's state (see
+ * MDPL_RUN_CONTINUE; row 0 of thermo is then that state's, taken from the
+ * previous run's last row when it sampled its last step).  At every rebuild
+ * the particles are reordered by cell IN PLACE in all ten arrays (positions folded into [0, L)), so that
  * ids[k] always holds the original id of the particle in slot k.
  * thermo: nullable; if sample_every > 0 it receives
  * (nsteps / sample_every + 1) rows of 4 doubles: KE, PE, virial, and the
  * largest displacement of any particle from its position at the list build,
  * over the reuse periods completed so far; rows are taken at step 0 and
  * every sample_every steps (KE after the second half kick).  On sampled
- * steps the force pass also forms PE and the virial in FP64.  A displacement
- * reaching skin/2 (a pair inside rc could be missing from the list; the
- * extended-cutoff condition of Eq. extended_cutoff bounds it by
- * n dt v_max) raises MDPL_FLAG_SKIN; see mdpl_check. */
+ * steps the force pass also forms PE and the virial in FP64.  If the last
+ * positions used with a list had moved skin/2 or more from those of its
+ * build (a pair inside rc could then be missing from the list),
+ * MDPL_FLAG_SKIN is raised; see mdpl_check.  The MDPL_REBUILD_VMAX rule
+ * rebuilds before that can happen (Eq. extended_cutoff). */
 mdpl_status mdpl_run(mdpl_sim* sim, double* x, double* y, double* z, double* vx, double* vy,
                      double* vz, void* fx, void* fy, void* fz, int32_t* ids, int64_t nsteps,
-                     int32_t sample_every, double* thermo);
+                     int32_t sample_every, double* thermo, int32_t start);
 
 /* mdpl_run with the Andersen thermostat of the crystallisation run (Sec.
  * 5.2; the paper gives neither the collision rule nor the random numbers,
@@ -199,7 +237,7 @@ mdpl_status mdpl_run_andersen(mdpl_sim* sim, double* x, double* y, double* z, do
                               double* vy, double* vz, void* fx, void* fy, void* fz, int32_t* ids,
                               int64_t nsteps, int32_t sample_every, double* thermo,
                               double temperature, double collision_rate, uint64_t seed,
-                              int64_t step0);
+                              int64_t step0, int32_t start);
 
 /* Synchronise the stream and read the device flags (MDPL_FLAG_* bits) and
  * the largest neighbour count seen (so max_nb can be raised).  Returns
@@ -211,12 +249,21 @@ mdpl_status mdpl_check(mdpl_sim* sim, uint32_t* flags_host, int32_t* max_count_h
 mdpl_status mdpl_clear_flags(mdpl_sim* sim);
 
 /* Kernel timing on the context's stream with HIP events.  When on, mdpl_run
- * brackets every launch of the force kernels with an event pair.
+ * brackets every launch of the force kernels with an event pair; on > 1
+ * creates events for that many launches up front, so that none is created
+ * while a timed run is enqueued (events are reused afterwards).
  * mdpl_kernel_time synchronises and returns the summed milliseconds and the
  * number of launches for `which` = 0 (plain force pass) or 1 (force pass
  * with energy and virial), then resets the record. */
 mdpl_status mdpl_set_timing(mdpl_sim* sim, int32_t on);
 mdpl_status mdpl_kernel_time(mdpl_sim* sim, int32_t which, double* ms_host, int64_t* launches_host);
+
+/* Rebuilds of the runs of this context so far (host counters, no
+ * synchronisation): all, those the VMAX rule made before reuse_every steps,
+ * and the times the host waited for the stream to decide.  Any output may
+ * be NULL. */
+mdpl_status mdpl_rebuild_stats(mdpl_sim* sim, int64_t* rebuilds_host, int64_t* early_host,
+                               int64_t* syncs_host);
 
 /* Number of neighbour-list entries of the current list (sum of the
  * per-particle counts), after mdpl_build or mdpl_run.  Synchronises. */
@@ -237,15 +284,23 @@ mdpl_status mdpl_boa(const double* x, const double* y, const double* z, int64_t 
                      int32_t* nnb, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Common-neighbour analysis (Sec. 4.2, Eqs. Ei and Ei_ordered; Algs. cna_I,
- * cna_II, cna_III and max_cluster_size).  max_nb <= 32.  Per particle:
- * nnb[i] = number of bonds (may exceed max_nb; then only the label is set,
- * to OTHER), trip[i*max_nb + k] for k < min(nnb, max_nb) = the triplets of
- * its bonds packed as (n_cn << 20) | (n_b << 10) | n_lcb, sorted ascending;
- * label[i] = 0 other, 1 fcc, 2 hcp, 3 bcc. */
+ * cna_II, cna_III and max_cluster_size).  1 <= max_nb <= 64 is the capacity
+ * of a particle's bond list (the static size of Sec. 4.2, which must cover
+ * the largest bond count for every triplet to be computed).  Per particle:
+ * nnb[i] = number of bonds (may exceed max_nb); if nnb[i] <= max_nb,
+ * trip[i*max_nb + k] for k < nnb[i] = the triplets of its bonds packed as
+ * (n_cn << 20) | (n_b << 10) | n_lcb, sorted ascending (entries k >= nnb[i]
+ * are not written), exact whatever the bond counts of its neighbours (the
+ * bonds among its neighbours are tested directly); if nnb[i] > max_nb, no
+ * triplets are written.  label[i] = 0 other, 1 fcc, 2 hcp, 3 bcc; every
+ * reference signature has 12 or 14 bonds, so labels are exact for all
+ * particles whenever max_nb >= 14.  max_count (device, nullable) receives
+ * the largest bond count of any particle, so that a caller can see that
+ * max_nb covered every particle or repeat with a larger one. */
 mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t n,
                      const double* box_host, double rc, int32_t max_nb, uint32_t* trip,
-                     int32_t* nnb, uint8_t* label, void* workspace, size_t workspace_bytes,
-                     void* stream);
+                     int32_t* nnb, uint8_t* label, int32_t* max_count, void* workspace,
+                     size_t workspace_bytes, void* stream);
 
 
 /* ------------------------------------------------------- learned potential
@@ -331,7 +386,7 @@ mdpl_status mdpl_mlp_run_floats(int64_t n, int64_t* floats_host);
 mdpl_status mdpl_run_mlp(mdpl_sim* sim, const mdpl_mlp_weights* w, float* ws, int64_t ws_floats,
                          double* x, double* y, double* z, double* vx, double* vy, double* vz,
                          float* fx, float* fy, float* fz, int32_t* ids, int64_t nsteps,
-                         int32_t sample_every, double* thermo);
+                         int32_t sample_every, double* thermo, int32_t start);
 
 /* out[0] = sum_i |f_i - g_i|^2, out[1] = sum_i |g_i|^2 over the sim's n
  * particles (FP64, fixed order): the force error of one force field (f,

@@ -178,7 +178,7 @@ def wrap(pos, box):
 
 def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float = 1.0, sigma: float = 1.0,
                     mass: float = 1.0, shift: str = "none", sample_every: int = 0, force_fn=None,
-                    andersen=None):
+                    andersen=None, record_vmax: bool = False):
     """Velocity Verlet exactly in the order of Alg. VelocityVerlet.
 
     force_fn(x) -> dict(F, pe, w) replaces the LJ force field when given
@@ -196,7 +196,11 @@ def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float
     |dx| < 1.5 L).  Thermo samples (step, KE, PE, W) are taken at step 0 and
     every ``sample_every`` steps after the second half kick.
 
-    Returns dict(pos, vel, F, thermo (S,4))."""
+    record_vmax: also return vmax, the largest speed |v| of each step's
+    drift (the velocities after its first half kick), the input of the
+    list-reuse rule (``rebuild_schedule``).
+
+    Returns dict(pos, vel, F, thermo (S,4)[, vmax (nsteps,)])."""
     x = np.array(pos, dtype=np.float64, copy=True)
     v = np.array(vel, dtype=np.float64, copy=True)
     h = dt / (2.0 * mass)
@@ -208,8 +212,11 @@ def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float
     thermo = []
     if sample_every:
         thermo.append((0, kinetic_energy(v, mass), res["pe"], res["w"]))
+    vmax = []
     for step in range(1, nsteps + 1):
         v = v + h * F
+        if record_vmax:
+            vmax.append(float(np.max(np.sqrt(np.sum(v * v, axis=1)))))
         x = x + dt * v
         res = force_fn(x)
         F = res["F"]
@@ -219,7 +226,34 @@ def velocity_verlet(pos, vel, box, nsteps: int, dt: float, rc: float, eps: float
         if andersen is not None:
             v, _ = thermostat.andersen(v, andersen["ids"], andersen["step0"] + step, andersen["temperature"],
                                        andersen["nu"], dt, andersen["seed"], mass)
-    return {"pos": x, "vel": v, "F": F, "thermo": np.array(thermo, dtype=np.float64).reshape(-1, 4)}
+    out = {"pos": x, "vel": v, "F": F, "thermo": np.array(thermo, dtype=np.float64).reshape(-1, 4)}
+    if record_vmax:
+        out["vmax"] = np.array(vmax)
+    return out
+
+
+def rebuild_schedule(vmax, dt: float, skin: float, reuse_every: int, bound: float = 0.0,
+                     since: int = 0):
+    """Steps at which the lists are rebuilt under the reuse rule of Eq.
+    extended_cutoff (Sec. 3.5): a list built with the extra shell delta =
+    skin stays valid for n steps while 2 n dt v_max < delta.  Read per step:
+    after the drift of step k, with B = sum over the steps since the last
+    build of dt * vmax[k] (the largest speed of the velocities that moved
+    the particles in that step), the list is rebuilt before the force pass
+    of step k if 2 B >= skin, or if reuse_every steps have passed since the
+    last build (the largest reuse count given with delta).  ``vmax[k - 1]``
+    is step k's speed (k = 1 .. len(vmax)); ``bound`` and ``since`` carry a
+    period over from an earlier call.  Returns (list of rebuild steps,
+    bound, since) at the end."""
+    steps = []
+    for k, v in enumerate(vmax, start=1):
+        bound += dt * float(v)
+        since += 1
+        if since >= reuse_every or 2.0 * bound >= skin:
+            steps.append(k)
+            bound = 0.0
+            since = 0
+    return steps, bound, since
 
 
 def sc_shell_energy(a: float, rc: float, eps: float = 1.0, sigma: float = 1.0, shift: str = "none") -> float:

@@ -14,8 +14,9 @@
 //
 // Common-neighbour analysis (Sec. 4.2, Algs. cna_I to cna_III and
 // max_cluster_size): one thread per particle i.  The bonds among the
-// neighbours of i are gathered once into adjacency bit masks over N(i)
-// (bit b of adj[a] <=> neighbour a bonded to neighbour b).  For the bond
+// neighbours of i are found once, by the exact bond test between every two
+// members of N(i), and kept as adjacency bit masks over N(i) (bit b of
+// adj[a] <=> neighbour a bonded to neighbour b).  For the bond
 // (i, j = N(i)[b]): common neighbours C = adj[b] (members of N(i) bonded to
 // j), n_cn = |C|, n_b = half the degree sum inside C, and n_lcb = largest
 // number of edges in a connected component of C, by mask flood fill.  All
@@ -152,21 +153,47 @@ hipError_t boa_q(const double* sx, const double* sy, const double* sz, const int
 
 // ------------------------------------------------------------------- CNA
 constexpr int kCnaThreads = 64;
-constexpr int kCnaMax = 32;
+constexpr int kCnaMax = 64;
 
 __device__ __forceinline__ uint32_t pack_triplet(int ncn, int nb, int nlcb) {
   return ((uint32_t)ncn << 20) | ((uint32_t)nb << 10) | (uint32_t)nlcb;
 }
 
-// MAXNB: LDS columns per thread (16 or 32); fewer columns, more waves per CU.
-template <int MAXNB>
-__global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const int32_t* __restrict__ perm,
+template <typename M>
+__device__ __forceinline__ int popc_mask(M m) {
+  if constexpr (sizeof(M) == 8) return __popcll(m);
+  else return __popc(m);
+}
+template <typename M>
+__device__ __forceinline__ int lowest_bit(M m) {
+  if constexpr (sizeof(M) == 8) return __ffsll((long long)m) - 1;
+  else return __ffs(m) - 1;
+}
+
+// MAXNB: LDS columns per thread (16, 32 or 64); M: adjacency mask type with
+// at least MAXNB bits.  Fewer columns, more waves per CU.
+//
+// The adjacency among N(i) (bonds with both ends in N(i), i.e. the part of
+// Ebar(i) that any triplet of i can read) is formed from the exact FP64 bond
+// test between every two members of N(i), on the stored positions.  It
+// therefore needs only the complete list of i itself: an atom with at most
+// max_nb bonds gets its exact triplets whatever the bond counts of its
+// neighbours.  An atom with more than max_nb bonds gets no triplets and the
+// label OTHER (every reference signature has 12 or 14 bonds, so the label
+// is exact whenever max_nb >= 14).
+template <int MAXNB, typename M>
+__global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const double* __restrict__ sx,
+                                                     const double* __restrict__ sy,
+                                                     const double* __restrict__ sz, Grid g,
+                                                     double rc2, const int32_t* __restrict__ perm,
                                                      int64_t n, uint32_t* __restrict__ trip,
                                                      int32_t* __restrict__ nnb,
                                                      uint8_t* __restrict__ label, int max_out) {
-  // per-thread columns: L[k][tid] neighbour k of i; adj[k][tid] its mask
+  static_assert(8 * sizeof(M) >= MAXNB, "mask narrower than the list");
+  // per-thread columns: L[k][tid] member k of N(i) (later the triplet codes);
+  // adj[k][tid] the members bonded to member k
   __shared__ int32_t L[MAXNB][kCnaThreads];
-  __shared__ uint32_t adj[MAXNB][kCnaThreads];
+  __shared__ M adj[MAXNB][kCnaThreads];
   const int tid = threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * kCnaThreads + tid;
   if (s >= n) return;
@@ -179,58 +206,47 @@ __global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const int32_t* __
     return;
   }
   const int32_t* row = nl.nbr + s * (int64_t)max_nb;
-  // N(i) in ascending slot order (insertion sort), so that membership is a
-  // binary search; the triplets count bonds and do not depend on the order
   for (int k = 0; k < ni; ++k) {
-    const int32_t v = row[k];
-    int b = k - 1;
-    while (b >= 0 && L[b][tid] > v) {
-      L[b + 1][tid] = L[b][tid];
-      --b;
-    }
-    L[b + 1][tid] = v;
+    L[k][tid] = row[k];
+    adj[k][tid] = 0;
   }
-  // adjacency among the neighbours of i (bonds of Ebar(i) with both ends in N(i))
+  const double Lx = g.box[0], Ly = g.box[1], Lz = g.box[2];
+  const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
   for (int a = 0; a < ni; ++a) {
-    const int32_t v = L[a][tid];
-    const int nv0 = nl.cnt[v];
-    const int nv = nv0 > max_nb ? max_nb : nv0;
-    const int32_t* rv = nl.nbr + (int64_t)v * max_nb;
-    uint32_t mask = 0;
-    for (int q = 0; q < nv; ++q) {
-      const int32_t w = rv[q];
-      int lo = 0, hi = ni;  // first index with L >= w
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (L[mid][tid] < w) lo = mid + 1;
-        else hi = mid;
+    const int32_t va = L[a][tid];
+    const double xa = sx[va], ya = sy[va], za = sz[va];
+    M ma = adj[a][tid];
+    for (int b = a + 1; b < ni; ++b) {
+      const int32_t vb = L[b][tid];
+      if (exact_d2(xa, ya, za, sx[vb], sy[vb], sz[vb], Lx, Ly, Lz, hx, hy, hz) < rc2) {
+        ma |= (M)1 << b;
+        adj[b][tid] |= (M)1 << a;
       }
-      if (lo < ni && L[lo][tid] == w) mask |= 1u << lo;
     }
-    adj[a][tid] = mask;
+    adj[a][tid] = ma;
   }
   // triplet of every bond (i, N(i)[b]); codes reuse the L column
   uint32_t* code = (uint32_t*)&L[0][0];
   for (int b = 0; b < ni; ++b) {
-    const uint32_t cm = adj[b][tid];
-    const int ncn = __popc(cm);
+    const M cm = adj[b][tid];  // common neighbours of i and N(i)[b]
+    const int ncn = popc_mask(cm);
     int deg = 0;
-    for (uint32_t r = cm; r; r &= r - 1) deg += __popc(adj[__ffs(r) - 1][tid] & cm);
+    for (M r = cm; r; r &= r - 1) deg += popc_mask(adj[lowest_bit(r)][tid] & cm);
     const int nbonds = deg >> 1;
     int best = 0;
-    uint32_t rem = cm;
+    M rem = cm;
     while (rem) {
-      uint32_t comp = rem & (~rem + 1u);
-      uint32_t front = comp;
+      M comp = rem & (~rem + (M)1);
+      M front = comp;
       while (front) {
-        uint32_t nxt = 0;
-        for (uint32_t r = front; r; r &= r - 1) nxt |= adj[__ffs(r) - 1][tid] & cm;
+        M nxt = 0;
+        for (M r = front; r; r &= r - 1) nxt |= adj[lowest_bit(r)][tid] & cm;
         nxt &= ~comp;
         comp |= nxt;
         front = nxt;
       }
       int e2 = 0;
-      for (uint32_t r = comp; r; r &= r - 1) e2 += __popc(adj[__ffs(r) - 1][tid] & comp);
+      for (M r = comp; r; r &= r - 1) e2 += popc_mask(adj[lowest_bit(r)][tid] & comp);
       const int edges = e2 >> 1;
       best = edges > best ? edges : best;
       rem &= ~comp;
@@ -265,14 +281,20 @@ __global__ __launch_bounds__(kCnaThreads) void k_cna(NList nl, const int32_t* __
   label[o] = lab;
 }
 
-hipError_t cna_signatures(const NList& nl, const int32_t* perm, int64_t n, uint32_t* trip,
-                          int32_t* nnb, uint8_t* label, int max_out, hipStream_t st) {
+hipError_t cna_signatures(const NList& nl, const double* sx, const double* sy, const double* sz,
+                          const Grid& g, double rc2, const int32_t* perm, int64_t n,
+                          uint32_t* trip, int32_t* nnb, uint8_t* label, int max_out,
+                          hipStream_t st) {
+  const dim3 grid((unsigned)div_up(n, kCnaThreads)), block(kCnaThreads);
   if (nl.max_nb <= 16)
-    hipLaunchKernelGGL(k_cna<16>, dim3((unsigned)div_up(n, kCnaThreads)), dim3(kCnaThreads), 0, st,
-                       nl, perm, n, trip, nnb, label, max_out);
+    hipLaunchKernelGGL((k_cna<16, uint32_t>), grid, block, 0, st, nl, sx, sy, sz, g, rc2, perm, n,
+                       trip, nnb, label, max_out);
+  else if (nl.max_nb <= 32)
+    hipLaunchKernelGGL((k_cna<32, uint32_t>), grid, block, 0, st, nl, sx, sy, sz, g, rc2, perm, n,
+                       trip, nnb, label, max_out);
   else
-    hipLaunchKernelGGL(k_cna<kCnaMax>, dim3((unsigned)div_up(n, kCnaThreads)), dim3(kCnaThreads), 0,
-                       st, nl, perm, n, trip, nnb, label, max_out);
+    hipLaunchKernelGGL((k_cna<kCnaMax, uint64_t>), grid, block, 0, st, nl, sx, sy, sz, g, rc2,
+                       perm, n, trip, nnb, label, max_out);
   return hipGetLastError();
 }
 

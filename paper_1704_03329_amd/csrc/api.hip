@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -29,7 +30,18 @@ int32_t g_last_hip_error = 0;
 
 struct Timing {
   std::vector<hipEvent_t> ev[2];  // start/stop pairs, flattened
+  std::vector<hipEvent_t> pool;   // created, not recorded (reused across timed runs)
 };
+
+// run kinds whose state a continued run may take over
+constexpr int kKindLJ = 1, kKindMLP = 2;
+
+// The rule's host decision (see run_loop): records older than kLagMax steps
+// make the host wait (without draining the stream) until the device is
+// within kLagKeep steps; the prediction allows the largest speed of the
+// recent records to double before the next record is seen.
+constexpr int64_t kLagMax = 48, kLagKeep = 16;
+constexpr double kSpeedHeadroom = 2.0;
 
 }  // namespace
 
@@ -63,6 +75,27 @@ struct mdpl_sim {
   bool have_list;
   bool timing;
   Timing tm;
+  // run continuation: the arrays and kind of the last run (valid until an
+  // mdpl_build or a failed run)
+  struct {
+    bool valid;
+    int kind;
+    StateArrays arrays;
+  } resume;
+  int64_t gstep;           // global step index of the current positions
+  int64_t kb;              // gstep of the last list build of a run
+  int64_t since;           // steps since that build
+  bool have_ref;           // xb holds the positions of that build
+  double* last_row;        // device: thermo row of the last step of the last run
+  bool last_row_valid;
+  // rebuild rule of Eq. extended_cutoff
+  unsigned long long* vstep;
+  unsigned int* done;
+  double* bound;
+  KickRecord* ring_host;   // pinned, host-mapped
+  KickRecord* ring_dev;
+  KickTrack track;         // for the next drifting launch
+  int64_t n_rebuilds, n_early, n_syncs;
 };
 
 extern "C" {
@@ -103,6 +136,7 @@ mdpl_status validate(const mdpl_lj_params* p) {
   if (p->max_nb < 1 || p->max_nb > 1024) return MDPL_EINVAL;
   if (p->pairs != MDPL_PAIRS_FULL && p->pairs != MDPL_PAIRS_HALF && p->pairs != MDPL_PAIRS_CELLS)
     return MDPL_EINVAL;
+  if (p->rebuild != MDPL_REBUILD_FIXED && p->rebuild != MDPL_REBUILD_VMAX) return MDPL_EINVAL;
   Grid g;
   int unit[3] = {1, 1, 1};
   return make_grid(p->box, p->rc + p->skin, unit, &g);
@@ -152,7 +186,7 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += align256(4 * (size_t)npad);             // cnt
   b += align256(4 * (size_t)(n + 1));          // offsets
   b += align256(8 * (size_t)(3 * nblk + 2));   // partials
-  b += align256(64);                           // flags, maxcount, max_disp, pe_w_tmp
+  b += align256(256);                          // flags, maxcount, max_disp, pe_w_tmp, rule, last row
   b += align256(4 * 8 * (size_t)g.nbricks);   // brick order of the tile kernels
   return b;
 }
@@ -211,6 +245,16 @@ double shift_value(const mdpl_lj_params* p) {
   return 0.0;
 }
 
+// An event from the pool (created only when the pool is empty).
+hipError_t take_event(mdpl_sim* s, hipEvent_t* e) {
+  if (!s->tm.pool.empty()) {
+    *e = s->tm.pool.back();
+    s->tm.pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
 // kick (nullable): fuse the velocity-Verlet kick-kick-drift of the next step
 // into the force pass (velocities of *kick updated, new positions to spare,
 // KE of the sampled step to ke_dst); forces are then not stored.
@@ -238,10 +282,12 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
   out.h = s->p.dt / (2.0 * s->p.mass);
   out.dt = s->p.dt;
   out.flags = s->flags;
+  out.track = s->track;
+  if (!out.fuse) out.track.ring = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (s->timing && timing_slot >= 0) {
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(take_event(s, &e0));
+    HIP_TRY(take_event(s, &e1));
     HIP_TRY(hipEventRecord(e0, s->st));
   }
   int nb = 0;
@@ -350,7 +396,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
   s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
   s->partials = take<double>(w, 8 * (size_t)(3 * s->nblk + 2));
-  char* small = take<char>(w, 64);
+  char* small = take<char>(w, 256);
   {
     const std::vector<int32_t> order = brick_order(s->g);
     int32_t* dorder = take<int32_t>(w, 4 * 8 * (size_t)s->g.nbricks);
@@ -367,12 +413,42 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->maxcount = (int32_t*)(small + 4);
   s->max_disp = (double*)(small + 8);
   s->pe_w_tmp = (double*)(small + 16);
+  s->vstep = (unsigned long long*)(small + 32);
+  s->done = (unsigned int*)(small + 40);
+  s->bound = (double*)(small + 48);
+  s->last_row = (double*)(small + 64);
   s->built = false;
   s->have_list = false;
   s->timing = false;
-  hipError_t e = hipMemsetAsync(small, 0, 64, s->st);
+  s->resume.valid = false;
+  s->gstep = s->kb = s->since = 0;
+  s->have_ref = false;
+  s->last_row_valid = false;
+  s->n_rebuilds = s->n_early = s->n_syncs = 0;
+  s->ring_host = s->ring_dev = nullptr;
+  {
+    // the rule's records: pinned host memory the kernels write through
+    void* h = nullptr;
+    hipError_t e = hipHostMalloc(&h, sizeof(KickRecord) * kRing,
+                                 hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+      memset(h, 0, sizeof(KickRecord) * kRing);
+      for (int q = 0; q < kRing; ++q) ((KickRecord*)h)[q].stamp = -1;
+      e = hipHostGetDevicePointer((void**)&s->ring_dev, h, 0);
+    }
+    if (e != hipSuccess) {
+      if (h) (void)hipHostFree(h);
+      g_last_hip_error = (int32_t)e;
+      delete s;
+      return MDPL_EHIP;
+    }
+    s->ring_host = (KickRecord*)h;
+  }
+  s->track = KickTrack{s->vstep, s->done, s->bound, nullptr, 0, p->dt};
+  hipError_t e = hipMemsetAsync(small, 0, 256, s->st);
   if (e != hipSuccess) {
     g_last_hip_error = (int32_t)e;
+    (void)hipHostFree(s->ring_host);
     delete s;
     return MDPL_EHIP;
   }
@@ -382,14 +458,19 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
 
 mdpl_status mdpl_sim_destroy(mdpl_sim* s) {
   if (!s) return MDPL_EINVAL;
+  // the kernels may still write the records: finish the stream first
+  (void)hipStreamSynchronize(s->st);
   for (int k = 0; k < 2; ++k)
     for (hipEvent_t e : s->tm.ev[k]) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->tm.pool) (void)hipEventDestroy(e);
+  if (s->ring_host) (void)hipHostFree(s->ring_host);
   delete s;
   return MDPL_OK;
 }
 
 mdpl_status mdpl_build(mdpl_sim* s, const double* x, const double* y, const double* z) {
   if (!s || !x || !y || !z) return MDPL_EINVAL;
+  s->resume.valid = false;
   int32_t *skeys, *svals;
   HIP_TRY(bin_particles(x, y, z, s->n, s->g, s->sort, s->cell_start, &skeys, &svals, s->st));
   HIP_TRY(hipMemcpyAsync(s->perm, svals, 4 * (size_t)s->n, hipMemcpyDeviceToDevice, s->st));
@@ -400,6 +481,7 @@ mdpl_status mdpl_build(mdpl_sim* s, const double* x, const double* y, const doub
                              s->flags, s->maxcount, s->st));
   s->built = true;
   s->have_list = !s->tl.cells;
+  s->resume.valid = false;  // the list of the last run is overwritten
   return MDPL_OK;
 }
 
@@ -485,8 +567,15 @@ mdpl_status mdpl_clear_flags(mdpl_sim* s) {
 }
 
 mdpl_status mdpl_set_timing(mdpl_sim* s, int32_t on) {
-  if (!s) return MDPL_EINVAL;
+  if (!s || on < 0) return MDPL_EINVAL;
   s->timing = on != 0;
+  // reserve event pairs so that no event is created while timing
+  const size_t want = on > 1 ? 4 * (size_t)on : 0;
+  while (s->tm.pool.size() < want) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    s->tm.pool.push_back(e);
+  }
   return MDPL_OK;
 }
 
@@ -502,8 +591,16 @@ mdpl_status mdpl_kernel_time(mdpl_sim* s, int32_t which, double* ms, int64_t* la
   }
   if (ms) *ms = tot;
   if (launches) *launches = (int64_t)(v.size() / 2);
-  for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  for (hipEvent_t e : v) s->tm.pool.push_back(e);
   v.clear();
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_rebuild_stats(mdpl_sim* s, int64_t* rebuilds, int64_t* early, int64_t* syncs) {
+  if (!s) return MDPL_EINVAL;
+  if (rebuilds) *rebuilds = s->n_rebuilds;
+  if (early) *early = s->n_early;
+  if (syncs) *syncs = s->n_syncs;
   return MDPL_OK;
 }
 
@@ -511,16 +608,123 @@ mdpl_status mdpl_kernel_time(mdpl_sim* s, int32_t which, double* ms, int64_t* la
 
 namespace {
 
+// One record of the rule's ring, read consistently (the stamp before and
+// after the fields); false if the device was writing it.
+bool read_record(const KickRecord* p, KickRecord* out) {
+  const int64_t a = __atomic_load_n(&p->stamp, __ATOMIC_ACQUIRE);
+  out->bound = ((const volatile KickRecord*)p)->bound;
+  out->vmax = ((const volatile KickRecord*)p)->vmax;
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  const int64_t b = __atomic_load_n(&p->stamp, __ATOMIC_ACQUIRE);
+  out->stamp = a;
+  return a == b && a >= 0;
+}
+
+// The newest record the device has published (stamp <= upto) and the largest
+// speed of all records in the ring.
+bool latest_record(const mdpl_sim* s, int64_t upto, KickRecord* out, double* vref) {
+  bool have = false;
+  *vref = 0.0;
+  for (int q = 0; q < kRing; ++q) {
+    KickRecord r;
+    if (!read_record(s->ring_host + q, &r) || r.stamp > upto) continue;
+    *vref = r.vmax > *vref ? r.vmax : *vref;
+    if (!have || r.stamp > out->stamp) {
+      *out = r;
+      have = true;
+    }
+  }
+  return have;
+}
+
+// Waits (without draining the stream) until the device has published the
+// record of step `target` or a later one.
+mdpl_status wait_record(mdpl_sim* s, int64_t target) {
+  for (int64_t it = 0;; ++it) {
+    KickRecord r;
+    double v;
+    if (latest_record(s, INT64_MAX, &r, &v) && r.stamp >= target) return MDPL_OK;
+    if ((it & 1023) == 1023) {
+      const hipError_t q = hipStreamQuery(s->st);
+      if (q == hipSuccess) return MDPL_OK;  // idle: nothing more will come
+      (void)hipGetLastError();              // a not-ready query is not an error of the library
+      if (q != hipErrorNotReady) {
+        g_last_hip_error = (int32_t)q;
+        return MDPL_EHIP;
+      }
+    }
+    std::this_thread::yield();
+  }
+}
+
+// The rebuild rule of Eq. extended_cutoff for the positions of step k =
+// s->gstep: rebuild when 2 * bound >= skin, bound = sum over the steps since
+// the last build of dt * max|v| (the device's records).  The host predicts
+// the bound from the newest record it can see, allowing the largest recent
+// speed to double in the steps it cannot see yet; only when that prediction
+// reaches the threshold does it wait for the stream and decide on the exact
+// record of step k.  So the rebuilds are those of the rule itself, unless a
+// speed more than doubles within the host's lag (the displacement check at
+// every rebuild still flags a list used too long).
+mdpl_status rule_decide(mdpl_sim* s, bool* need) {
+  const int64_t k = s->gstep;
+  const double dt = s->p.dt, skin = s->p.skin;
+  KickRecord r;
+  double vref = 0.0;
+  bool have = latest_record(s, k, &r, &vref);
+  if (have && k - r.stamp > kLagMax) {
+    const mdpl_status e = wait_record(s, k - kLagKeep);
+    if (e != MDPL_OK) return e;
+    have = latest_record(s, k, &r, &vref);
+  }
+  if (have) {
+    const double base = r.stamp > s->kb ? r.bound : 0.0;
+    const int64_t from = r.stamp > s->kb ? r.stamp : s->kb;
+    const double pred = base + (double)(k - from) * dt * (kSpeedHeadroom * vref);
+    if (2.0 * pred < skin) {
+      *need = false;
+      return MDPL_OK;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s->st));
+  ++s->n_syncs;
+  KickRecord rk;
+  if (!read_record(s->ring_host + (k & (kRing - 1)), &rk) || rk.stamp != k) {
+    *need = true;  // no record of this step: rebuild to be safe
+    return MDPL_OK;
+  }
+  *need = 2.0 * rk.bound >= skin;
+  return MDPL_OK;
+}
+
+bool same_arrays(const StateArrays& a, const StateArrays& b) {
+  return a.x == b.x && a.y == b.y && a.z == b.z && a.vx == b.vx && a.vy == b.vy && a.vz == b.vz &&
+         a.fx == b.fx && a.fy == b.fy && a.fz == b.fz && a.ids == b.ids;
+}
+
 // The time loop of Alg. VelocityVerlet with list reuse (Sec. 3.5), shared by
 // the LJ and learned-potential runs.  force(cur, energy, pe_w_dst, slot, fuse,
 // spare, ke_dst, disp_dst) fills cur.f* from cur positions (on sampled steps
 // also PE, W into pe_w_dst and the maximum displacement since the last build
-// into disp_dst).
+// into disp_dst); with fuse it also applies the next step's kick-kick-drift,
+// the new positions going to spare.
 // th (nullable): Andersen collisions after every completed step; global
 // step numbers start at th->step (the step0 of mdpl_run_andersen) + 1.
+// start: MDPL_RUN_SETUP bins, builds and computes F(r0) first;
+// MDPL_RUN_CONTINUE takes over the state that the last run of this kind left
+// in the same arrays (list, forces, step count since the build).
+// Positions are double-buffered (the drift writes to the spare buffer), so
+// that at a rebuild the positions of the last force pass with the old list
+// are still there for the displacement check.
 template <typename ForceFn>
 mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t sample_every,
-                     double* thermo, bool can_fuse, ForceFn force, const Andersen* th = nullptr) {
+                     double* thermo, bool can_fuse, ForceFn force, int kind, int32_t start,
+                     const Andersen* th = nullptr) {
+  if (start != MDPL_RUN_SETUP && start != MDPL_RUN_CONTINUE) return MDPL_EINVAL;
+  const bool cont = start == MDPL_RUN_CONTINUE;
+  if (cont && !(s->resume.valid && s->resume.kind == kind && same_arrays(s->resume.arrays, user)))
+    return MDPL_ESTATE;
+  s->resume.valid = false;  // until this run has been enqueued completely
   const int64_t n = s->n;
   const int prec = s->p.precision;
   const int ns = s->p.reuse_every;
@@ -528,45 +732,79 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
   const double h = dt / (2.0 * s->p.mass);
   const double half_skin = 0.5 * s->p.skin;
   const double ke_scale = 0.5 * s->p.mass;
+  const bool rule = s->p.rebuild == MDPL_REBUILD_VMAX;
   StateArrays alt{s->sx, s->sy, s->sz, s->avx, s->avy, s->avz, s->afx, s->afy, s->afz, s->aids};
   StateArrays cur = user, other = alt;
   double* spare[3] = {s->px, s->py, s->pz};
   Andersen thermo_cfg{};
-  bool have_ref = false;
   s->built = false;  // the standalone build is overwritten
+  s->track.ring = rule ? s->ring_dev : nullptr;
 
-  auto rebuild = [&]() -> mdpl_status {
-    if (have_ref) {
+  // check: the displacement of the last force pass with the old list (in
+  // spare, the drift's other buffer) against half the skin
+  auto rebuild = [&](bool check, bool early) -> mdpl_status {
+    if (check && s->have_ref) {
       int nb = 0;
-      HIP_TRY(disp_partials(cur.x, cur.y, cur.z, s->xb, s->yb, s->zb, n, s->partials, s->st, &nb));
+      HIP_TRY(disp_partials(spare[0], spare[1], spare[2], s->xb, s->yb, s->zb, n, s->partials,
+                            s->st, &nb));
       HIP_TRY(skin_check(s->partials, nb, half_skin, s->max_disp, s->flags, s->st));
     }
     int32_t *skeys, *svals;
     HIP_TRY(bin_particles(cur.x, cur.y, cur.z, n, s->g, s->sort, s->cell_start, &skeys, &svals,
                           s->st));
-    HIP_TRY(reorder_state(cur, svals, n, s->fbytes, s->p.box, other, s->xb, s->yb, s->zb, s->st));
+    HIP_TRY(reorder_state(cur, svals, n, s->fbytes, s->p.box, other, s->xb, s->yb, s->zb,
+                          s->bound, s->st));
     StateArrays t = cur;
     cur = other;
     other = t;
     if (!s->tl.cells)
       HIP_TRY(build_tile_nlist(cur.x, cur.y, cur.z, skeys, s->cell_start, s->g, s->r2ext, s->tl,
                                s->flags, s->maxcount, s->st));
-    have_ref = true;
+    s->have_ref = true;
     s->have_list = !s->tl.cells;
+    s->kb = s->gstep;
+    s->since = 0;
+    ++s->n_rebuilds;
+    if (early) ++s->n_early;
     return MDPL_OK;
   };
   auto row = [&](int64_t step) { return thermo + 4 * (step / sample_every); };
   auto sampled = [&](int64_t step) { return sample_every > 0 && step % sample_every == 0; };
+  auto swap_positions = [&]() {
+    double* t[3] = {cur.x, cur.y, cur.z};
+    cur.x = spare[0];
+    cur.y = spare[1];
+    cur.z = spare[2];
+    spare[0] = t[0];
+    spare[1] = t[1];
+    spare[2] = t[2];
+  };
 
-  mdpl_status r = rebuild();
-  if (r != MDPL_OK) return r;
-  r = force(cur, sampled(0), sampled(0) ? row(0) + 1 : nullptr, -1, false, spare, nullptr,
-            sampled(0) ? row(0) + 3 : nullptr);
-  if (r != MDPL_OK) return r;
+  mdpl_status r = MDPL_OK;
+  if (!cont) {
+    r = rebuild(false, false);
+    if (r != MDPL_OK) return r;
+    r = force(cur, sampled(0), sampled(0) ? row(0) + 1 : nullptr, -1, false, spare, nullptr,
+              sampled(0) ? row(0) + 3 : nullptr);
+    if (r != MDPL_OK) return r;
+  } else if (sampled(0) && s->last_row_valid) {
+    // the positions are the last run's final ones, whose PE, W it sampled
+    // (the KE is formed again below: velocities may have been rescaled)
+    HIP_TRY(hipMemcpyAsync(row(0), s->last_row, 4 * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+  } else if (sampled(0)) {
+    // PE, W of the current state from a pass whose forces go to scratch
+    StateArrays tmp = cur;
+    tmp.fx = other.fx;
+    tmp.fy = other.fy;
+    tmp.fz = other.fz;
+    r = force(tmp, true, row(0) + 1, -1, false, spare, nullptr, row(0) + 3);
+    if (r != MDPL_OK) return r;
+  }
   if (sampled(0)) {
     int nb = 0;
-    HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
-                    h, dt, 3, true, s->partials, s->flags, s->st, &nb));
+    HIP_TRY(vv_step(cur.x, cur.y, cur.z, nullptr, nullptr, nullptr, cur.vx, cur.vy, cur.vz,
+                    cur.fx, cur.fy, cur.fz, prec, n, h, dt, 3, true, s->partials, s->flags, s->st,
+                    &nb));
     HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(0), ke_scale, s->st));
   }
   // the collisions at the end of global step g (the kick completing it is in vv_step)
@@ -582,41 +820,42 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     if (!fused) {
       const bool ke = step > 1 && sampled(step - 1);
       int nb = 0;
-      HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
-                      h, dt, step == 1 ? 0 : 1, ke, s->partials, s->flags, s->st, &nb,
-                      step == 1 ? nullptr : collide(step - 1)));
+      s->track.step = s->gstep + 1;
+      HIP_TRY(vv_step(cur.x, cur.y, cur.z, spare[0], spare[1], spare[2], cur.vx, cur.vy, cur.vz,
+                      cur.fx, cur.fy, cur.fz, prec, n, h, dt, step == 1 ? 0 : 1, ke, s->partials,
+                      s->flags, s->st, &nb, step == 1 ? nullptr : collide(step - 1), &s->track));
+      swap_positions();
       if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(step - 1), ke_scale, s->st));
     }
-    if (step % ns == 0) {
-      r = rebuild();
+    ++s->gstep;
+    ++s->since;
+    bool need = s->since >= ns, early = false;
+    if (!need && rule) {
+      r = rule_decide(s, &need);
+      if (r != MDPL_OK) return r;
+      early = need;
+    }
+    if (need) {
+      r = rebuild(true, early);
       if (r != MDPL_OK) return r;
     }
     const bool en = sampled(step);
     // the pass of the last step stores its forces for the final half kick
     fused = can_fuse && step < nsteps;
+    s->track.step = s->gstep + 1;
     r = force(cur, en, en ? row(step) + 1 : nullptr, en ? 1 : 0, fused, spare,
               en ? row(step) : nullptr, en ? row(step) + 3 : nullptr);
     if (r != MDPL_OK) return r;
-    if (fused) {
-      double* t[3] = {cur.x, cur.y, cur.z};
-      cur.x = spare[0];
-      cur.y = spare[1];
-      cur.z = spare[2];
-      spare[0] = t[0];
-      spare[1] = t[1];
-      spare[2] = t[2];
-    }
+    if (fused) swap_positions();
   }
   if (nsteps > 0) {
     const bool ke = sampled(nsteps);
     int nb = 0;
-    HIP_TRY(vv_step(cur.x, cur.y, cur.z, cur.vx, cur.vy, cur.vz, cur.fx, cur.fy, cur.fz, prec, n,
-                    h, dt, 2, ke, s->partials, s->flags, s->st, &nb, collide(nsteps)));
+    HIP_TRY(vv_step(cur.x, cur.y, cur.z, nullptr, nullptr, nullptr, cur.vx, cur.vy, cur.vz,
+                    cur.fx, cur.fy, cur.fz, prec, n, h, dt, 2, ke, s->partials, s->flags, s->st,
+                    &nb, collide(nsteps)));
     if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(nsteps), ke_scale, s->st));
-  }
-  // close the last reuse period
-  {
-    int nb = 0;
+    // close the last reuse period: the final positions were used by the last pass
     HIP_TRY(disp_partials(cur.x, cur.y, cur.z, s->xb, s->yb, s->zb, n, s->partials, s->st, &nb));
     HIP_TRY(skin_check(s->partials, nb, half_skin, s->max_disp, s->flags, s->st));
   }
@@ -638,6 +877,13 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     HIP_TRY(back(user.fz, cur.fz, fb));
     HIP_TRY(back(user.ids, cur.ids, 4 * (size_t)n));
   }
+  s->last_row_valid = sampled(nsteps);
+  if (s->last_row_valid)
+    HIP_TRY(hipMemcpyAsync(s->last_row, row(nsteps), 4 * sizeof(double), hipMemcpyDeviceToDevice,
+                           s->st));
+  s->resume.valid = true;
+  s->resume.kind = kind;
+  s->resume.arrays = user;
   return MDPL_OK;
 }
 
@@ -647,7 +893,7 @@ extern "C" {
 
 mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, double* vy,
                      double* vz, void* fx, void* fy, void* fz, int32_t* ids, int64_t nsteps,
-                     int32_t sample_every, double* thermo) {
+                     int32_t sample_every, double* thermo, int32_t start) {
   if (!s || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids) return MDPL_EINVAL;
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
   const int prec = s->p.precision;
@@ -660,14 +906,15 @@ mdpl_status mdpl_run(mdpl_sim* s, double* x, double* y, double* z, double* vx, d
                     return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr,
                                         en, nullptr, pe_w, prec, slot, fuse ? &cur : nullptr,
                                         spare, ke, disp);
-                  });
+                  },
+                  kKindLJ, start);
 }
 
 mdpl_status mdpl_run_andersen(mdpl_sim* s, double* x, double* y, double* z, double* vx,
                               double* vy, double* vz, void* fx, void* fy, void* fz, int32_t* ids,
                               int64_t nsteps, int32_t sample_every, double* thermo,
                               double temperature, double collision_rate, uint64_t seed,
-                              int64_t step0) {
+                              int64_t step0, int32_t start) {
   if (!s || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids) return MDPL_EINVAL;
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo) || step0 < 0) return MDPL_EINVAL;
   const double p = collision_rate * s->p.dt;
@@ -684,7 +931,7 @@ mdpl_status mdpl_run_andersen(mdpl_sim* s, double* x, double* y, double* z, doub
         return launch_force(s, cur.x, cur.y, cur.z, cur.fx, cur.fy, cur.fz, nullptr, en, nullptr,
                             pe_w, prec, slot, nullptr, nullptr, nullptr, disp);
       },
-      &th);
+      kKindLJ, start, &th);
 }
 
 // ------------------------------------------------------------ analysis
@@ -768,8 +1015,8 @@ mdpl_status mdpl_boa(const double* x, const double* y, const double* z, int64_t 
 
 mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t n,
                      const double* box, double rc, int32_t max_nb, uint32_t* trip, int32_t* nnb,
-                     uint8_t* label, void* ws, size_t bytes, void* stream) {
-  if (!trip || !nnb || !label || max_nb < 1 || max_nb > 32) return MDPL_EINVAL;
+                     uint8_t* label, int32_t* max_count, void* ws, size_t bytes, void* stream) {
+  if (!trip || !nnb || !label || max_nb < 1 || max_nb > 64) return MDPL_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   Grid g;
   SortBufs sb;
@@ -782,7 +1029,9 @@ mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t 
   if (v != MDPL_OK) return v;
   HIP_TRY(hipMemsetAsync(small, 0, 64, st));
   HIP_TRY(build_nlist(sx, sy, sz, skeys, cs, n, g, rc * rc, nl, small, (int32_t*)(small + 1), st));
-  HIP_TRY(cna_signatures(nl, perm, n, trip, nnb, label, max_nb, st));
+  HIP_TRY(cna_signatures(nl, sx, sy, sz, g, rc * rc, perm, n, trip, nnb, label, max_nb, st));
+  if (max_count)
+    HIP_TRY(hipMemcpyAsync(max_count, small + 1, 4, hipMemcpyDeviceToDevice, st));
   return MDPL_OK;
 }
 
@@ -887,7 +1136,7 @@ mdpl_status mdpl_mlp_run_floats(int64_t n, int64_t* floats) {
 mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int64_t ws_floats,
                          double* x, double* y, double* z, double* vx, double* vy, double* vz,
                          float* fx, float* fy, float* fz, int32_t* ids, int64_t nsteps,
-                         int32_t sample_every, double* thermo) {
+                         int32_t sample_every, double* thermo, int32_t start) {
   if (!s || !mlp_ok(w) || !ws || !x || !y || !z || !vx || !vy || !vz || !fx || !fy || !fz || !ids)
     return MDPL_EINVAL;
   if (nsteps < 0 || sample_every < 0 || (sample_every > 0 && !thermo)) return MDPL_EINVAL;
@@ -905,8 +1154,8 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
                       double* const*, double*, double* disp) -> mdpl_status {
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (s->timing && slot >= 0) {
-                      HIP_TRY(hipEventCreate(&e0));
-                      HIP_TRY(hipEventCreate(&e1));
+                      HIP_TRY(take_event(s, &e0));
+                      HIP_TRY(take_event(s, &e1));
                       HIP_TRY(hipEventRecord(e0, s->st));
                     }
                     HIP_TRY(desc_forward(cur.x, cur.y, cur.z, s->cell_start, s->g, s->tl, rc,
@@ -937,7 +1186,8 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
                       HIP_TRY(reduce_row(s->partials, nb, 1, 1, o, s->st));
                     }
                     return MDPL_OK;
-                  });
+                  },
+                  kKindMLP, start);
 }
 
 mdpl_status mdpl_force_error(mdpl_sim* s, const float* fx, const float* fy, const float* fz,

@@ -343,8 +343,9 @@ hipError_t gather_canonical(const double* x, const double* y, const double* z, c
 template <typename FT>
 __global__ void k_reorder(StateArrays src, const int32_t* __restrict__ idx, int64_t n, double Lx,
                           double Ly, double Lz, StateArrays dst, double* xb, double* yb,
-                          double* zb) {
+                          double* zb, double* bound) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bound && s == 0) *bound = 0.0;
   if (s >= n) return;
   const int32_t j = idx[s];
   const double a = fold(src.x[j], Lx), b = fold(src.y[j], Ly), c = fold(src.z[j], Lz);
@@ -367,14 +368,14 @@ __global__ void k_reorder(StateArrays src, const int32_t* __restrict__ idx, int6
 
 hipError_t reorder_state(const StateArrays& src, const int32_t* idx, int64_t n, int fbytes,
                          const double* box, StateArrays& dst, double* xb, double* yb, double* zb,
-                         hipStream_t st) {
+                         double* bound, hipStream_t st) {
   const unsigned nb = (unsigned)div_up(n, 256);
   if (fbytes == 4)
     hipLaunchKernelGGL(k_reorder<float>, dim3(nb), dim3(256), 0, st, src, idx, n, box[0], box[1],
-                       box[2], dst, xb, yb, zb);
+                       box[2], dst, xb, yb, zb, bound);
   else
     hipLaunchKernelGGL(k_reorder<double>, dim3(nb), dim3(256), 0, st, src, idx, n, box[0], box[1],
-                       box[2], dst, xb, yb, zb);
+                       box[2], dst, xb, yb, zb, bound);
   return hipGetLastError();
 }
 

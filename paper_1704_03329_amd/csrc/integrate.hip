@@ -60,17 +60,20 @@ __device__ __forceinline__ void andersen_collide(const Andersen& th, int64_t s, 
 // ------------------------------------------------------------ velocity Verlet
 // Listing position_update / velocity_update: v += F dt/(2m); r += dt v.
 template <typename FT>
-__global__ __launch_bounds__(256) void k_vv(double* __restrict__ x, double* __restrict__ y,
-                                            double* __restrict__ z, double* __restrict__ vx,
-                                            double* __restrict__ vy, double* __restrict__ vz,
-                                            const FT* __restrict__ fx, const FT* __restrict__ fy,
-                                            const FT* __restrict__ fz, int64_t n, double h,
-                                            double dt, int mode, int ke, double* ke_part,
-                                            uint32_t* flags, Andersen th) {
+__global__ __launch_bounds__(256) void k_vv(const double* __restrict__ x,
+                                            const double* __restrict__ y,
+                                            const double* __restrict__ z, double* __restrict__ nx,
+                                            double* __restrict__ ny, double* __restrict__ nz,
+                                            double* __restrict__ vx, double* __restrict__ vy,
+                                            double* __restrict__ vz, const FT* __restrict__ fx,
+                                            const FT* __restrict__ fy, const FT* __restrict__ fz,
+                                            int64_t n, double h, double dt, int mode, int ke,
+                                            double* ke_part, uint32_t* flags, Andersen th,
+                                            KickTrack kt) {
 #pragma clang fp contract(off)
   __shared__ double sh[4];
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double k = 0.0;
+  double k = 0.0, m2 = 0.0;
   if (s < n) {
     double a = vx[s], b = vy[s], cc = vz[s];
     if (mode != 3) {
@@ -86,14 +89,14 @@ __global__ __launch_bounds__(256) void k_vv(double* __restrict__ x, double* __re
         cc = cc + gz;
       }
       if (mode != 2) {
-        x[s] = x[s] + dt * a;
-        y[s] = y[s] + dt * b;
-        z[s] = z[s] + dt * cc;
+        nx[s] = x[s] + dt * a;
+        ny[s] = y[s] + dt * b;
+        nz[s] = z[s] + dt * cc;
       }
       vx[s] = a;
       vy[s] = b;
       vz[s] = cc;
-      const double m2 = (a * a + b * b) + cc * cc;
+      m2 = (a * a + b * b) + cc * cc;
       if (!(m2 < 1e300)) atomicOr(flags, MDPL_FLAG_NONFINITE);
     } else {
       k = (a * a + b * b) + cc * cc;
@@ -103,24 +106,31 @@ __global__ __launch_bounds__(256) void k_vv(double* __restrict__ x, double* __re
     const double t = block_sum256(k, sh);
     if (threadIdx.x == 0) ke_part[blockIdx.x] = t;
   }
+  if (mode == 0 || mode == 1) {
+    const double mb = block_max256(m2, sh);  // NaN propagates as the largest bit pattern
+    if (threadIdx.x == 0) kick_track(kt, mb);
+  }
 }
 
-hipError_t vv_step(double* x, double* y, double* z, double* vx, double* vy, double* vz,
-                   const void* fx, const void* fy, const void* fz, int precision, int64_t n,
-                   double h, double dt, int mode, bool ke, double* ke_partials, uint32_t* flags,
-                   hipStream_t st, int* nblocks_out, const Andersen* th) {
+hipError_t vv_step(const double* x, const double* y, const double* z, double* nx, double* ny,
+                   double* nz, double* vx, double* vy, double* vz, const void* fx, const void* fy,
+                   const void* fz, int precision, int64_t n, double h, double dt, int mode, bool ke,
+                   double* ke_partials, uint32_t* flags, hipStream_t st, int* nblocks_out,
+                   const Andersen* th, const KickTrack* track) {
   const unsigned nb = (unsigned)div_up(n, 256);
   if (nblocks_out) *nblocks_out = (int)nb;
   const Andersen none{nullptr, 0.0, 0.0, 0, 0};
   const Andersen& a = th ? *th : none;
+  KickTrack kt{};
+  if (track) kt = *track;
   if (precision == 1)
-    hipLaunchKernelGGL(k_vv<float>, dim3(nb), dim3(256), 0, st, x, y, z, vx, vy, vz,
+    hipLaunchKernelGGL(k_vv<float>, dim3(nb), dim3(256), 0, st, x, y, z, nx, ny, nz, vx, vy, vz,
                        (const float*)fx, (const float*)fy, (const float*)fz, n, h, dt, mode,
-                       ke ? 1 : 0, ke_partials, flags, a);
+                       ke ? 1 : 0, ke_partials, flags, a, kt);
   else
-    hipLaunchKernelGGL(k_vv<double>, dim3(nb), dim3(256), 0, st, x, y, z, vx, vy, vz,
+    hipLaunchKernelGGL(k_vv<double>, dim3(nb), dim3(256), 0, st, x, y, z, nx, ny, nz, vx, vy, vz,
                        (const double*)fx, (const double*)fy, (const double*)fz, n, h, dt, mode,
-                       ke ? 1 : 0, ke_partials, flags, a);
+                       ke ? 1 : 0, ke_partials, flags, a, kt);
   return hipGetLastError();
 }
 

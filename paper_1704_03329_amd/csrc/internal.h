@@ -92,10 +92,11 @@ struct StateArrays {
   int32_t* ids;
 };
 // dst[s] = src[idx[s]] for all ten arrays, positions folded into the box;
-// xb/yb/zb (nullable) receive a copy of the folded positions.
+// xb/yb/zb (nullable) receive a copy of the folded positions; bound
+// (nullable) is set to zero (a new list: nothing has moved since).
 hipError_t reorder_state(const StateArrays& src, const int32_t* idx, int64_t n, int fbytes,
                          const double* box, StateArrays& dst, double* xb, double* yb, double* zb,
-                         hipStream_t st);
+                         double* bound, hipStream_t st);
 
 // Neighbour list (ELL) of the analysis passes: row-major nbr[i * max_nb + m]
 // of sorted-slot indices; cnt[i] is the true count (may exceed max_nb).
@@ -152,6 +153,50 @@ struct LJConst {
   double box[3], half[3], inv_box[3];
 };
 
+// Rebuild rule of Eq. extended_cutoff: the kernel that drifts the positions
+// (the fused force pass or k_vv) records the largest speed of the step and
+// keeps bound = sum over the steps since the last build of dt * max|v|, an
+// upper bound of every particle's displacement since then.  The last
+// workgroup of the launch adds the step's term and publishes
+// {bound, max|v|} with the global step index in a ring of host-visible
+// records, so that the host can decide on a rebuild without waiting for the
+// stream.  The rebuild (k_reorder) sets bound back to zero.
+struct KickRecord {
+  int64_t stamp;  // global step index of the positions the drift produced (-1: empty)
+  double bound;   // sum of dt * max|v| since the last build, this step included
+  double vmax;    // largest speed of the step
+  double pad;
+};
+constexpr int kRing = 64;  // records kept (indexed by stamp mod kRing)
+struct KickTrack {
+  unsigned long long* vstep;  // device: bits of the step's largest |v|^2 (non-negative double)
+  unsigned int* done;         // device: workgroups of the launch that have finished
+  double* bound;              // device
+  KickRecord* ring;           // host-visible records (device address); null: no tracking
+  int64_t step;               // global step index of the positions produced
+  double dt;
+};
+// Called by one thread of every workgroup of a drifting launch with the
+// workgroup's largest |v|^2 (0 for a workgroup without particles).
+__device__ inline void kick_track(const KickTrack& kt, double m2) {
+  if (!kt.ring) return;
+  atomicMax(kt.vstep, (unsigned long long)__double_as_longlong(m2));
+  __threadfence();
+  const unsigned prev = atomicAdd(kt.done, 1u);
+  if (prev != gridDim.x - 1) return;
+  __threadfence();
+  const unsigned long long bits = atomicExch(kt.vstep, 0ull);
+  atomicExch(kt.done, 0u);
+  const double vmax = sqrt(__longlong_as_double((long long)bits));
+  const double b = *kt.bound + kt.dt * vmax;
+  *kt.bound = b;
+  KickRecord* r = kt.ring + (kt.step & (kRing - 1));
+  r->bound = b;
+  r->vmax = vmax;
+  __threadfence_system();
+  __hip_atomic_store(&r->stamp, kt.step, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 struct ForceOut {
   void *fx, *fy, *fz;     // force arrays (float or double)
   const int32_t* scatter; // nullable: slot s writes to scatter[s]
@@ -166,6 +211,7 @@ struct ForceOut {
   double *nx, *ny, *nz;   // new positions (a different buffer from x, y, z)
   double h, dt;
   uint32_t* flags;        // MDPL_FLAG_NONFINITE on a non-finite velocity; tile overflow (no list)
+  KickTrack track;        // fused drift: the step's largest speed (rebuild rule)
 };
 // Partials are written per brick (nblocks_out = number of bricks).
 hipError_t lj_force(const double* x, const double* y, const double* z, const int32_t* cell_start,
@@ -193,14 +239,18 @@ struct Andersen {
   uint64_t seed;
   int64_t step;        // global index of the step that the kick completes
 };
-//   mode 0: v += h F ; r += dt v                          (first step)
-//   mode 1: v += h F ; [KE] ; [collide] ; v += h F ; r += dt v   (fused end+start)
-//   mode 2: v += h F ; [KE] ; [collide]                   (final half kick)
+//   mode 0: v += h F ; r' = r + dt v                          (first step)
+//   mode 1: v += h F ; [KE] ; [collide] ; v += h F ; r' = r + dt v   (fused end+start)
+//   mode 2: v += h F ; [KE] ; [collide]                       (final half kick)
 //   mode 3: KE only
-hipError_t vv_step(double* x, double* y, double* z, double* vx, double* vy, double* vz,
-                   const void* fx, const void* fy, const void* fz, int precision, int64_t n,
-                   double h, double dt, int mode, bool ke, double* ke_partials, uint32_t* flags,
-                   hipStream_t st, int* nblocks_out, const Andersen* th = nullptr);
+// The drifted positions r' go to nx, ny, nz (a buffer other than x, y, z, so
+// that the positions of the last force pass survive the step); modes 0 and
+// 1 report the step's largest speed to track (nullable).
+hipError_t vv_step(const double* x, const double* y, const double* z, double* nx, double* ny,
+                   double* nz, double* vx, double* vy, double* vz, const void* fx, const void* fy,
+                   const void* fz, int precision, int64_t n, double h, double dt, int mode, bool ke,
+                   double* ke_partials, uint32_t* flags, hipStream_t st, int* nblocks_out,
+                   const Andersen* th = nullptr, const KickTrack* track = nullptr);
 
 // out[0] = sum of partials[k * stride + comp] over k, fixed order, one block.
 hipError_t reduce_partials(const double* partials, int nblocks, int stride, int ncomp,
@@ -234,8 +284,12 @@ hipError_t boa_q(const double* sx, const double* sy, const double* sz, const int
                  const int32_t* cell_start, const int32_t* perm, int64_t n, const Grid& g,
                  double rc2, float* q4, float* q5, float* q6, int32_t* nnb, hipStream_t st);
 
-hipError_t cna_signatures(const NList& nl, const int32_t* perm, int64_t n, uint32_t* trip,
-                          int32_t* nnb, uint8_t* label, int max_out, hipStream_t st);
+// CNA of every particle from its complete list (adjacency among its
+// neighbours from the exact bond test on the sorted positions sx, sy, sz).
+hipError_t cna_signatures(const NList& nl, const double* sx, const double* sy, const double* sz,
+                          const Grid& g, double rc2, const int32_t* perm, int64_t n,
+                          uint32_t* trip, int32_t* nnb, uint8_t* label, int max_out,
+                          hipStream_t st);
 
 
 // Learned potential: descriptors (desc.hip) and dense layers (mlp.hip).

@@ -33,10 +33,11 @@
 namespace mdpl {
 
 // The kick-kick-drift of k_vv mode 1 for one particle, same operations in
-// the same order; returns |v|^2 after the first kick (the sampled KE).
+// the same order; returns |v|^2 after the first kick (the sampled KE) and
+// sets m2 = |v|^2 of the velocity of the drift.
 __device__ __forceinline__ double fused_kick(const ForceOut& out, int64_t s, double xi, double yi,
                                              double zi, double a, double b, double cc, double fx,
-                                             double fy, double fz) {
+                                             double fy, double fz, double& m2) {
 #pragma clang fp contract(off)
   const double gx = out.h * fx, gy = out.h * fy, gz = out.h * fz;
   a = a + gx;
@@ -52,9 +53,27 @@ __device__ __forceinline__ double fused_kick(const ForceOut& out, int64_t s, dou
   out.vx[s] = a;
   out.vy[s] = b;
   out.vz[s] = cc;
-  const double m2 = (a * a + b * b) + cc * cc;
+  m2 = (a * a + b * b) + cc * cc;
   if (!(m2 < 1e300)) atomicOr(out.flags, MDPL_FLAG_NONFINITE);
   return k;
+}
+
+// Largest |v|^2 of the workgroup (v2 per thread, 0 where none) to the rule's
+// tracking; one barrier.
+__device__ __forceinline__ void block_track(const KickTrack& kt, double v2, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v2, off, 64);
+    v2 = o > v2 ? o : v2;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double m = sh[0];
+    for (int k = 1; k < nw; ++k) m = sh[k] > m ? sh[k] : m;
+    kick_track(kt, m);
+  }
 }
 
 // One workgroup per brick: the tile holds the image positions of the brick's
@@ -74,8 +93,12 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
   using Tile = std::conditional_t<ENERGY, TileShared, TileXY>;
   __shared__ Tile t;
   __shared__ double red[48];  // up to 16 waves: e, w, ke
+  __shared__ double vred[16];
   const int brick = brick_of_block(g);
-  if (brick >= g.nbricks) return;
+  if (brick >= g.nbricks) {  // padding workgroup: still counted by the rule's tracking
+    if (out.fuse && threadIdx.x == 0) kick_track(out.track, 0.0);
+    return;
+  }
   const int total = tile_cells(g, brick, cs, t);
   if constexpr (ENERGY) tile_load<true>(g, x, y, z, total, t);
   else tile_load_xy(g, x, y, z, total, t);
@@ -85,7 +108,7 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
   const MT fa = (MT)(48.0 * c.eps * sig6 * sig6), fb = (MT)(24.0 * c.eps * sig6);
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
-  double e = 0.0, w = 0.0, ke = 0.0;
+  double e = 0.0, w = 0.0, ke = 0.0, vmax2 = 0.0;
   // two lanes per particle, each taking every other list word (more waves in flight)
   constexpr int LPP = 2;
   const int part = (int)threadIdx.x % LPP;
@@ -182,8 +205,10 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
         vzi = out.vz[s];
       }
       // the kicks use the force as stored (rounded to OT), like k_vv
+      double m2;
       ke += fused_kick(out, s, xi, yi, zi, vxi, vyi, vzi, (double)(OT)(ax * scale),
-                       (double)(OT)(ay * scale), (double)(OT)(az * scale));
+                       (double)(OT)(ay * scale), (double)(OT)(az * scale), m2);
+      vmax2 = m2 > vmax2 ? m2 : vmax2;
       if (ENERGY) e += ei;
       continue;
     }
@@ -196,6 +221,7 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
       e += ei;
     }
   }
+  if (out.fuse && out.track.ring) block_track(out.track, vmax2, vred);
   if (ENERGY) {
     // brick sums: wave butterflies, then the wave sums in order
     e = wave_sum(e);

@@ -24,6 +24,8 @@ FLAG_NL_OVERFLOW, FLAG_SKIN, FLAG_NONFINITE = 1, 2, 4
 SHIFTS = {"none": 0, "paper": 1, "cutoff": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 PAIRS = {"full": 0, "half": 1, "cells": 2}
+REBUILD = {"fixed": 0, "vmax": 1}
+RUN_SETUP, RUN_CONTINUE = 0, 1
 
 
 class MdplError(RuntimeError):
@@ -51,6 +53,7 @@ class mdpl_lj_params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("max_nb", ctypes.c_int32),
         ("pairs", ctypes.c_int32),
+        ("rebuild", ctypes.c_int32),
     ]
 
 
@@ -69,15 +72,16 @@ _SIGS = {
     "mdpl_nlist_entries": ([_P, ctypes.POINTER(_I64)], _I32),
     "mdpl_forces": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "mdpl_lj_backward": ([_P, _P, _P, _P, _P, _P, _P, _P], _I32),
-    "mdpl_run": ([_P] + [_P] * 10 + [_I64, _I32, _P], _I32),
-    "mdpl_run_andersen": ([_P] + [_P] * 10 + [_I64, _I32, _P, _D, _D, ctypes.c_uint64, _I64], _I32),
+    "mdpl_run": ([_P] + [_P] * 10 + [_I64, _I32, _P, _I32], _I32),
+    "mdpl_run_andersen": ([_P] + [_P] * 10 + [_I64, _I32, _P, _D, _D, ctypes.c_uint64, _I64, _I32], _I32),
+    "mdpl_rebuild_stats": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)], _I32),
     "mdpl_check": ([_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_I32)], _I32),
     "mdpl_clear_flags": ([_P], _I32),
     "mdpl_set_timing": ([_P, _I32], _I32),
     "mdpl_kernel_time": ([_P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I32),
     "mdpl_analysis_workspace_bytes": ([_I64, ctypes.POINTER(_D), _D, _I32, ctypes.POINTER(_SZ)], _I32),
     "mdpl_boa": ([_P, _P, _P, _I64, ctypes.POINTER(_D), _D, _P, _P, _P, _P, _P, _SZ, _P], _I32),
-    "mdpl_cna": ([_P, _P, _P, _I64, ctypes.POINTER(_D), _D, _I32, _P, _P, _P, _P, _SZ, _P], _I32),
+    "mdpl_cna": ([_P, _P, _P, _I64, ctypes.POINTER(_D), _D, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
 }
 
 
@@ -138,7 +142,7 @@ def _stream(stream=None) -> int:
 
 
 def make_params(n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001, reuse_every=10,
-                shift="none", precision="fp32", max_nb=128, pairs="full") -> mdpl_lj_params:
+                shift="none", precision="fp32", max_nb=128, pairs="full", rebuild="vmax") -> mdpl_lj_params:
     p = mdpl_lj_params()
     p.n = int(n)
     for k in range(3):
@@ -149,6 +153,7 @@ def make_params(n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.max_nb = int(max_nb)
     p.pairs = PAIRS[pairs] if isinstance(pairs, str) else int(pairs)
+    p.rebuild = REBUILD[rebuild] if isinstance(rebuild, str) else int(rebuild)
     return p
 
 
@@ -201,18 +206,28 @@ def mdpl_lj_backward(sim: int, x, y, z, grad_e, gx, gy, gz):
 
 
 def mdpl_run(sim: int, x, y, z, vx, vy, vz, fx, fy, fz, ids, nsteps: int, sample_every: int = 0,
-             thermo=None):
+             thermo=None, start: int = RUN_SETUP):
     _check(lib().mdpl_run(sim, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(fx),
-                          _ptr(fy), _ptr(fz), _ptr(ids), int(nsteps), int(sample_every), _ptr(thermo)),
+                          _ptr(fy), _ptr(fz), _ptr(ids), int(nsteps), int(sample_every), _ptr(thermo),
+                          int(start)),
            "mdpl_run")
 
 
 def mdpl_run_andersen(sim: int, x, y, z, vx, vy, vz, fx, fy, fz, ids, nsteps: int, sample_every: int,
-                      thermo, temperature: float, collision_rate: float, seed: int, step0: int = 0):
+                      thermo, temperature: float, collision_rate: float, seed: int, step0: int = 0,
+                      start: int = RUN_SETUP):
     _check(lib().mdpl_run_andersen(sim, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(fx),
                                    _ptr(fy), _ptr(fz), _ptr(ids), int(nsteps), int(sample_every),
                                    _ptr(thermo), float(temperature), float(collision_rate),
-                                   int(seed) & ((1 << 64) - 1), int(step0)), "mdpl_run_andersen")
+                                   int(seed) & ((1 << 64) - 1), int(step0), int(start)), "mdpl_run_andersen")
+
+
+def mdpl_rebuild_stats(sim: int):
+    """Returns (rebuilds, early rebuilds of the VMAX rule, host waits for the stream)."""
+    a, b, c = _I64(0), _I64(0), _I64(0)
+    _check(lib().mdpl_rebuild_stats(sim, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "mdpl_rebuild_stats")
+    return int(a.value), int(b.value), int(c.value)
 
 
 def mdpl_check(sim: int, raise_on_error: bool = False):
@@ -229,8 +244,11 @@ def mdpl_clear_flags(sim: int):
     _check(lib().mdpl_clear_flags(sim), "mdpl_clear_flags")
 
 
-def mdpl_set_timing(sim: int, on: bool):
-    _check(lib().mdpl_set_timing(sim, 1 if on else 0), "mdpl_set_timing")
+def mdpl_set_timing(sim: int, on, reserve: int = 0):
+    """on: bool; reserve: launches to create events for up front (none are
+    then created while a timed run is enqueued)."""
+    _check(lib().mdpl_set_timing(sim, (max(int(reserve), 2) if reserve else 1) if on else 0),
+           "mdpl_set_timing")
 
 
 def mdpl_kernel_time(sim: int, which: int):
@@ -256,11 +274,12 @@ def mdpl_boa(x, y, z, box, rc, q4, q5, q6, nnb, workspace, stream=None):
            "mdpl_boa")
 
 
-def mdpl_cna(x, y, z, box, rc, max_nb, trip, nnb, label, workspace, stream=None):
+def mdpl_cna(x, y, z, box, rc, max_nb, trip, nnb, label, workspace, max_count=None, stream=None):
     n = x.numel()
     b = (_D * 3)(*[float(v) for v in box])
     _check(lib().mdpl_cna(_ptr(x), _ptr(y), _ptr(z), n, b, float(rc), int(max_nb), _ptr(trip), _ptr(nnb),
-                          _ptr(label), _dev(workspace, torch.uint8), workspace.numel(), _stream(stream)),
+                          _ptr(label), _ptr(max_count), _dev(workspace, torch.uint8), workspace.numel(),
+                          _stream(stream)),
            "mdpl_cna")
 
 
@@ -291,7 +310,8 @@ _SIGS_MLP = {
                               ctypes.c_int32),
     "mdpl_mlp_run_floats": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mdpl_run_mlp": ([ctypes.c_void_p, ctypes.POINTER(mdpl_mlp_weights), ctypes.c_void_p, ctypes.c_int64]
-                     + [ctypes.c_void_p] * 10 + [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
+                     + [ctypes.c_void_p] * 10 + [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32],
+                     ctypes.c_int32),
     "mdpl_force_error": ([ctypes.c_void_p] * 8, ctypes.c_int32),
 }
 _SIGS.update(_SIGS_MLP)
@@ -338,10 +358,11 @@ def mdpl_mlp_run_floats(n: int) -> int:
     return int(out.value)
 
 
-def mdpl_run_mlp(sim, w: mdpl_mlp_weights, ws, state: dict, nsteps: int, sample_every: int, thermo=None):
+def mdpl_run_mlp(sim, w: mdpl_mlp_weights, ws, state: dict, nsteps: int, sample_every: int, thermo=None,
+                 start: int = RUN_SETUP):
     _check(lib().mdpl_run_mlp(_handle(sim), ctypes.byref(w), _ptr(ws), ws.numel(),
                               *[_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "ids")],
-                              int(nsteps), int(sample_every), _ptr(thermo)), "mdpl_run_mlp")
+                              int(nsteps), int(sample_every), _ptr(thermo), int(start)), "mdpl_run_mlp")
 
 
 def mdpl_force_error(sim, fx, fy, fz, gx, gy, gz, out):

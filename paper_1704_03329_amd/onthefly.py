@@ -61,7 +61,7 @@ def crystallise(pos, vel, box, nve_steps=50_000, nvt_steps=500_000, boa_every=10
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         th = dict(temperature=t_bath, collision_rate=collision_rate, seed=seed, step0=step) if nvt else None
-        thermo = sim.run(state, block, block, andersen=th)
+        thermo = sim.run(state, block, block, andersen=th, cont=step > 0)
         torch.cuda.synchronize()
         md_s += time.perf_counter() - t0
         st, flags, _ = C.mdpl_check(sim.handle, False)

@@ -182,13 +182,15 @@ def generate_training_set(temperatures=(0.7, 1.0, 1.5), counts=(67, 67, 66), n_c
         run = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp64", shift="none")
         ref = LJSim(n, box, rc=2.5, skin=0.3, precision="fp64", shift="none")
         st = run.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
-        for _ in range(equil_steps // rescale_every):
-            th = run.run(st, rescale_every, rescale_every)
+        # each run continues the last one (list, forces, rebuild schedule);
+        # rescaling the velocities in between is allowed
+        for r in range(equil_steps // rescale_every):
+            th = run.run(st, rescale_every, rescale_every, cont=r > 0)
             ke = float(th[-1, 0].item())
             t_now = 2.0 * ke / (3.0 * (n - 1))
             mdpl_scale_velocities(st["vx"], st["vy"], st["vz"], (T / t_now) ** 0.5)
         for k in range(cnt):
-            run.run(st, every, 0)
+            run.run(st, every, 0, cont=True)
             pos = torch.stack([st["x"], st["y"], st["z"]], 1)
             e, F = lj_snapshot_targets(ref, pos)
             G = descriptors(ref, pos)
@@ -232,7 +234,7 @@ def mlp_md(model: MLPPotential, pos, vel, box, nsteps: int = 500, check_every: i
     C.mdpl_kernel_time(sim.handle, 1)
     for seg in range(nsteps // check_every):
         th = torch.empty((rows_per, 4), dtype=torch.float64, device=sim.device)
-        mdpl_run_mlp(sim, w, ws, st, check_every, sample_every, th)
+        mdpl_run_mlp(sim, w, ws, st, check_every, sample_every, th, start=1 if seg else 0)
         step = (seg + 1) * check_every
         thermo.append(th if seg == 0 else th[1:])
         ref.build(st["x"], st["y"], st["z"])

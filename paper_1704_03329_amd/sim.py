@@ -20,9 +20,10 @@ class LJSim:
     """A Lennard-Jones simulation context (mdpl_sim) with its workspace."""
 
     def __init__(self, n, box, rc=2.5, skin=0.3, eps=1.0, sigma=1.0, mass=1.0, dt=0.001, reuse_every=10,
-                 shift="none", precision="fp32", max_nb=128, pairs="full", device="cuda", stream=None):
+                 shift="none", precision="fp32", max_nb=128, pairs="full", rebuild="vmax", device="cuda",
+                 stream=None):
         self.params = C.make_params(n, box, rc, skin, eps, sigma, mass, dt, reuse_every, shift, precision,
-                                    max_nb, pairs)
+                                    max_nb, pairs, rebuild)
         self.n = int(n)
         self.box = [float(b) for b in box]
         self.device = torch.device(device)
@@ -79,21 +80,27 @@ class LJSim:
         return {"x": x, "y": y, "z": z, "vx": vx, "vy": vy, "vz": vz, "fx": f[0], "fy": f[1], "fz": f[2],
                 "ids": ids}
 
-    def run(self, state, nsteps, sample_every=0, andersen=None):
+    def run(self, state, nsteps, sample_every=0, andersen=None, cont=False):
         """nsteps of velocity Verlet; andersen: optional dict(temperature,
-        collision_rate, seed, step0) for mdpl_run_andersen."""
+        collision_rate, seed, step0) for mdpl_run_andersen; cont: continue
+        from the state the last run left in these arrays (MDPL_RUN_CONTINUE)."""
         thermo = None
         if sample_every:
             thermo = torch.zeros((nsteps // sample_every + 1, 4), dtype=torch.float64, device=self.device)
         s = state
         args = (self.handle, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["fx"], s["fy"], s["fz"],
                 s["ids"], nsteps, sample_every, thermo)
+        start = C.RUN_CONTINUE if cont else C.RUN_SETUP
         if andersen is None:
-            C.mdpl_run(*args)
+            C.mdpl_run(*args, start=start)
         else:
             C.mdpl_run_andersen(*args, andersen["temperature"], andersen["collision_rate"], andersen["seed"],
-                                andersen.get("step0", 0))
+                                andersen.get("step0", 0), start=start)
         return thermo
+
+    def rebuild_stats(self):
+        """(rebuilds, early rebuilds of the VMAX rule, host waits for the stream)."""
+        return C.mdpl_rebuild_stats(self.handle)
 
     def check(self, raise_on_error=True):
         return C.mdpl_check(self.handle, raise_on_error)
@@ -115,15 +122,18 @@ def boa(x, y, z, box, rc, q5=False):
 
 
 def cna(x, y, z, box, rc, max_nb=32):
-    """Common-neighbour analysis: dict(trip (N,max_nb) int32 codes, nnb, label)."""
+    """Common-neighbour analysis: dict(trip (N,max_nb) int32 codes, nnb, label,
+    max_count (device int32 scalar: the largest bond count; particles with
+    more than max_nb bonds have no triplets))."""
     n = x.numel()
     dev = x.device
     ws = torch.empty(C.mdpl_analysis_workspace_bytes(n, box, rc, max_nb), dtype=torch.uint8, device=dev)
     trip = torch.zeros((n, max_nb), dtype=torch.int32, device=dev)
     nnb = torch.empty(n, dtype=torch.int32, device=dev)
     label = torch.empty(n, dtype=torch.uint8, device=dev)
-    C.mdpl_cna(x, y, z, box, rc, max_nb, trip, nnb, label, ws)
-    return {"trip": trip, "nnb": nnb, "label": label}
+    most = torch.zeros(1, dtype=torch.int32, device=dev)
+    C.mdpl_cna(x, y, z, box, rc, max_nb, trip, nnb, label, ws, most)
+    return {"trip": trip, "nnb": nnb, "label": label, "max_count": most}
 
 
 def unpack_triplets(codes):

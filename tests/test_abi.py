@@ -102,7 +102,8 @@ def test_misaligned_workspace_rejected(lib):
 def test_null_handles_rejected(lib):
     assert lib.mdpl_sim_destroy(None) == C.MDPL_EINVAL
     assert lib.mdpl_build(None, None, None, None) == C.MDPL_EINVAL
-    assert lib.mdpl_run(None, *([None] * 10), 10, 0, None) == C.MDPL_EINVAL
+    assert lib.mdpl_run(None, *([None] * 10), 10, 0, None, 0) == C.MDPL_EINVAL
+    assert lib.mdpl_rebuild_stats(None, None, None, None) == C.MDPL_EINVAL
     assert lib.mdpl_check(None, None, None) == C.MDPL_EINVAL
     assert lib.mdpl_forces(None, *([None] * 8)) == C.MDPL_EINVAL
 
@@ -116,4 +117,4 @@ def test_analysis_validation(lib):
     assert lib.mdpl_analysis_workspace_bytes(0, box, 1.5, 32, ctypes.byref(out)) == C.MDPL_EINVAL
     assert lib.mdpl_analysis_workspace_bytes(1000, box, -1.0, 32, ctypes.byref(out)) == C.MDPL_EINVAL
     # CNA capacity limit is checked before any device work
-    assert lib.mdpl_cna(None, None, None, 10, box, 1.5, 33, None, None, None, None, 0, None) == C.MDPL_EINVAL
+    assert lib.mdpl_cna(None, None, None, 10, box, 1.5, 65, None, None, None, None, None, 0, None) == C.MDPL_EINVAL

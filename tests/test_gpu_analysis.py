@@ -44,6 +44,7 @@ def _cna_gpu(pos, box, rc, max_nb=32):
     from paper_1704_03329_amd.sim import cna
 
     gpu_device()
+    print(f"cna n={pos.shape[0]} max_nb={max_nb}", flush=True)
     r = cna(*split_dev(pos), box, rc, max_nb)
     return {k: v.cpu().numpy() for k, v in r.items()}
 
@@ -92,23 +93,60 @@ def test_cna_perfect_lattices(kind, label):
         assert got["label"][i] == labels[i]
 
 
-def test_cna_polycrystal_sampled(grains):
+@pytest.fixture(scope="module")
+def grains_cna(grains):
+    """Oracle CNA (literal sets) of every atom of the 20k polycrystal."""
+    sigs, labels = ocna.cna(grains["pos"], grains["box"], RCNA)
+    return sigs, labels
+
+
+@pytest.mark.parametrize("max_nb", [16, 32])
+def test_cna_polycrystal_all_atoms(grains, grains_cna, max_nb):
+    """Every atom against the oracle.  At capacity 16 about a tenth of the
+    atoms have more bonds: they get no triplets and the label OTHER (exact,
+    since every reference signature has 12 or 14 bonds), and the atoms next
+    to them, whose triplets read their bonds, must still be exact."""
     pos, box = grains["pos"], grains["box"]
-    got = _cna_gpu(pos, box, RCNA)
-    atoms = sorted(mdinputs.rng(4).choice(pos.shape[0], 400, replace=False).tolist())
-    sigs, labels = ocna.cna_sampled(pos, box, RCNA, atoms)
-    for i in atoms:
-        assert got["nnb"][i] == len(sigs[i])
-        assert _decode(got["trip"][i], got["nnb"][i]) == sigs[i], i
-        assert got["label"][i] == labels[i], i
-    # every label class occurs in a three-phase polycrystal
+    sigs, labels = grains_cna
+    n = pos.shape[0]
+    got = _cna_gpu(pos, box, RCNA, max_nb)
+    ref_nnb = np.array([len(sigs[i]) for i in range(n)])
+    ref_lab = np.array([labels[i] for i in range(n)])
+    assert np.array_equal(got["nnb"], ref_nnb)
+    assert np.array_equal(got["label"], ref_lab)
+    assert int(got["max_count"][0]) == ref_nnb.max()
+    for i in range(n):
+        if ref_nnb[i] <= max_nb:
+            assert _decode(got["trip"][i], ref_nnb[i]) == sigs[i], i
     assert set(np.unique(got["label"]).tolist()) >= {0, 1, 2, 3}
+    if max_nb == 16:
+        # the case a capacity-dependent adjacency gets wrong: atoms within
+        # capacity bonded to an atom beyond it
+        nb = ocna.neighbour_sets(pos, box, RCNA)
+        over = set(np.nonzero(ref_nnb > max_nb)[0].tolist())
+        next_to = [i for i in range(n) if ref_nnb[i] <= max_nb and nb[i] & over]
+        assert len(over) > 100 and len(next_to) > 100
+        for i in next_to:
+            assert _decode(got["trip"][i], ref_nnb[i]) == sigs[i], i
 
 
-def test_cna_overflow_reported():
-    pos, box = _lattice("bcc")
-    got = _cna_gpu(pos, box, RCNA, max_nb=10)
-    assert np.all(got["nnb"] == 14) and np.all(got["label"] == 0)
+def test_cna_wide_masks():
+    """More than 32 bonds per atom (64-bit adjacency masks): jittered FCC with
+    a cutoff between the third and fourth shells (d sqrt(3) and 2 d:
+    12 + 6 + 24 = 42 bonds), every atom."""
+    pos, box = mdinputs.fcc_cells((4, 4, 4), D * math.sqrt(2.0))
+    pos = mdinputs.perturb(pos, 0.01 * D, 17)
+    rc = 1.85 * D
+    got = _cna_gpu(pos, box, rc, 64)
+    sigs, labels = ocna.cna(pos, box, rc)
+    n = pos.shape[0]
+    ref_nnb = np.array([len(sigs[i]) for i in range(n)])
+    assert ref_nnb.min() > 32
+    assert np.array_equal(got["nnb"], ref_nnb)
+    assert int(got["max_count"][0]) == ref_nnb.max()
+    for i in range(n):
+        assert _decode(got["trip"][i], ref_nnb[i]) == sigs[i], i
+        assert got["label"][i] == labels[i]
 
 
 def test_analysis_large_sampled():
@@ -129,7 +167,9 @@ def test_analysis_large_sampled():
         assert c["label"][i] == labels[i]
         assert b["nnb"][i] == ref["nu"][k]
         assert abs(b["q4"][i] - ref[4][k]) <= 1e-5 and abs(b["q6"][i] - ref[6][k]) <= 1e-5
-    # BOA and CNA agree on bond counts, and most atoms are crystalline
+    # BOA and CNA agree on bond counts, the capacity covered every atom, and
+    # most atoms are crystalline
     assert np.array_equal(b["nnb"], c["nnb"])
+    assert int(c["max_count"][0]) == int(b["nnb"].max()) <= 32
     frac = np.bincount(c["label"], minlength=4) / n
     assert frac[1:].sum() > 0.5

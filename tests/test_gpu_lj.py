@@ -237,18 +237,106 @@ def test_run_deterministic_and_resumable():
         assert torch.equal(state[k], s1[k]), k
 
 
+def test_run_continue_bitwise():
+    """MDPL_RUN_CONTINUE: runs that go on from the last run's state (no
+    rebinning, no F(r0) pass, the rebuild schedule carried over) give the
+    state of one longer run bit for bit, also when a call ends inside a
+    reuse period."""
+    from paper_1704_03329_amd import mdpl as C
+
+    d = mdinputs.lj_fluid(10, temperature=1.0, seed=2)
+    box = d["box"]
+    mk = lambda: _sim(1000, box, rc=2.5, skin=0.3, reuse_every=10, precision="fp64")
+    s1, t1 = _run(mk(), d["pos"], d["vel"], 40, 10)
+    keys = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "ids")
+    sim = mk()
+    state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    sim.run(state, 20, 10)
+    t2 = sim.run(state, 20, 10, cont=True)
+    torch.cuda.synchronize()
+    for k in keys:
+        assert torch.equal(state[k], s1[k]), k
+    # rows of steps 30 and 40 come from the same passes as in the long run
+    assert torch.equal(t2[1:], t1[3:])
+    assert t2.shape == (3, 4)
+    sim = mk()
+    state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    for block in (13, 1, 19, 7):
+        sim.run(state, block, 0, cont=block != 13)
+    torch.cuda.synchronize()
+    for k in keys:
+        assert torch.equal(state[k], s1[k]), k
+    assert sim.rebuild_stats()[0] == 1 + 4  # the initial build and steps 10, 20, 30, 40
+    # other arrays, or a standalone build in between: no state to continue
+    other = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    with pytest.raises(C.MdplError) as e:
+        sim.run(other, 5, 0, cont=True)
+    assert e.value.status == C.MDPL_ESTATE
+    sim.build(state["x"], state["y"], state["z"])
+    with pytest.raises(C.MdplError) as e:
+        sim.run(state, 5, 0, cont=True)
+    assert e.value.status == C.MDPL_ESTATE
+
+
+def test_rule_rebuilds_early_and_matches_oracle():
+    """The reuse rule of Eq. extended_cutoff at dt 0.005 (the crystallisation
+    step): the lists are rebuilt whenever 2 sum dt v_max reaches the skin,
+    well before reuse_every = 18 steps.  The FP64 run matches the oracle to
+    1e-9 with no skin flag, and the rebuilds are those of the rule applied
+    to the oracle's own trajectory.  With the fixed schedule the same run
+    moves particles past skin/2 and is flagged."""
+    from paper_1704_03329_amd import mdpl as C
+
+    d = mdinputs.lj_fluid(10, temperature=1.0, seed=1)
+    box = d["box"]
+    nsteps, dt = 60, 0.005
+    sim = _sim(1000, box, rc=2.5, skin=0.3, dt=dt, reuse_every=18, precision="fp64", shift="cutoff",
+               rebuild="vmax")
+    state, thermo = _run(sim, d["pos"], d["vel"], nsteps, 10)
+    assert sim.check(raise_on_error=False)[0] == 0
+    ref = olj.velocity_verlet(d["pos"], d["vel"], box, nsteps, dt, 2.5, shift="cutoff", sample_every=10,
+                              record_vmax=True)
+    th = thermo.cpu().numpy()
+    for col in (0, 1, 2):
+        np.testing.assert_allclose(th[:, col], ref["thermo"][:, col + 1], rtol=1e-9, atol=1e-10)
+    assert np.all(th[:, 3] < 0.15)
+    x, v, f = _unpermute(state)
+    assert np.max(np.abs(_wrapdiff(x, ref["pos"], box))) < 1e-9
+    assert np.max(np.abs(v - ref["vel"])) < 1e-9
+    g, m = force_errors(f, ref["F"])
+    assert g < 1e-9 and m < 1e-9
+    steps, _, _ = olj.rebuild_schedule(ref["vmax"], dt, 0.3, 18)
+    gaps = np.diff([0] + steps)
+    rebuilds, early, _ = sim.rebuild_stats()
+    print(f"rebuild steps {steps}, device: {rebuilds} rebuilds, {early} early", flush=True)
+    assert np.all(gaps < 18)
+    assert rebuilds == 1 + len(steps) and early == int(np.sum(gaps < 18))
+    fixed = _sim(1000, box, rc=2.5, skin=0.3, dt=dt, reuse_every=18, precision="fp64", shift="cutoff",
+                 rebuild="fixed")
+    _run(fixed, d["pos"], d["vel"], nsteps, 0)
+    st, flags, _ = fixed.check(raise_on_error=False)
+    assert st == C.MDPL_ESKIN and flags & C.FLAG_SKIN
+
+
 def test_skin_violation_flagged():
+    """The displacement check that backs every rebuild: with the fixed
+    schedule one fast particle outruns the skin and is flagged; the VMAX rule
+    rebuilds in time for it."""
     from paper_1704_03329_amd import mdpl as C
 
     d = mdinputs.lj_fluid(10, temperature=0.5, seed=3)
     vel = d["vel"].copy()
     vel[123] = [25.0, 0.0, 0.0]  # moves 0.25 in 10 steps > skin/2 = 0.15
-    sim = _sim(1000, d["box"], rc=2.5, skin=0.3, reuse_every=10, precision="fp64")
+    sim = _sim(1000, d["box"], rc=2.5, skin=0.3, reuse_every=10, precision="fp64", rebuild="fixed")
     _run(sim, d["pos"], vel, 20, 0)
     st, flags, _ = sim.check(raise_on_error=False)
     assert st == C.MDPL_ESKIN and flags & C.FLAG_SKIN
+    rule = _sim(1000, d["box"], rc=2.5, skin=0.3, reuse_every=10, precision="fp64", rebuild="vmax")
+    _run(rule, d["pos"], vel, 20, 0)
+    assert rule.check(raise_on_error=False)[0] == 0
+    assert rule.rebuild_stats()[1] > 0
     # a calm run raises nothing
-    sim2 = _sim(1000, d["box"], rc=2.5, skin=0.3, reuse_every=10, precision="fp64")
+    sim2 = _sim(1000, d["box"], rc=2.5, skin=0.3, reuse_every=10, precision="fp64", rebuild="fixed")
     _run(sim2, d["pos"], d["vel"], 20, 0)
     assert sim2.check(raise_on_error=False)[0] == 0
 

@@ -262,3 +262,28 @@ def test_velocity_verlet_single_step_by_hand():
     res = lj.velocity_verlet(d["pos"], d["vel"], d["box"], 1, dt, 2.5)
     assert np.array_equal(res["pos"], x1)
     assert np.array_equal(res["vel"], v1)
+
+
+# ------------------------------------------------------------ rebuild rule
+def test_rebuild_schedule_constant_speed():
+    """Constant speed v: 2 n dt v >= skin first at n = ceil(skin / (2 dt v))
+    (Eq. extended_cutoff), so the rebuilds are equally spaced by n."""
+    for v, dt, skin in ((5.0, 0.005, 0.3), (3.3, 0.004, 0.25), (7.0, 0.001, 0.3)):
+        n = math.ceil(skin / (2.0 * dt * v) - 1e-12)
+        steps, _, _ = lj.rebuild_schedule([v] * 200, dt, skin, reuse_every=1000)
+        assert steps == list(range(n, 201, n)), (v, dt, skin, n, steps[:5])
+
+
+def test_rebuild_schedule_reuse_cap_and_carry():
+    # slow particles: only the reuse count rebuilds
+    steps, b, since = lj.rebuild_schedule([1.0] * 35, 0.001, 0.3, reuse_every=10)
+    assert steps == [10, 20, 30] and since == 5 and b == pytest.approx(5 * 0.001)
+    # splitting the speeds over two calls gives the same schedule
+    v = list(np.linspace(1.0, 9.0, 120))
+    whole, _, _ = lj.rebuild_schedule(v, 0.004, 0.3, reuse_every=18)
+    a, b, since = lj.rebuild_schedule(v[:47], 0.004, 0.3, reuse_every=18)
+    c, _, _ = lj.rebuild_schedule(v[47:], 0.004, 0.3, reuse_every=18, bound=b, since=since)
+    assert whole == a + [47 + k for k in c]
+    # a faster stretch shortens the periods
+    gaps = np.diff([0] + whole)
+    assert gaps[0] == 18 and gaps[-1] < 18
