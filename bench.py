@@ -338,6 +338,11 @@ def main():
     ap.add_argument("--pairs", choices=["full", "half", "cells"], default="full",
                     help="pair loop of the timed run: full lists, half lists (Newton's third law) "
                          "or no list (the cell stencil every pass)")
+    ap.add_argument("--rebuild", choices=["vmax", "fixed"], default="vmax",
+                    help="list reuse: every 10 steps or earlier by the rule of Eq. extended_cutoff "
+                         "(vmax), or every 10 steps only (fixed)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the run without per-launch events (no roofline line)")
     ap.add_argument("--no-pairs-compare", action="store_true",
                     help="skip the short runs of the other pair loops reported beside the main one")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -382,7 +387,7 @@ def main():
     log(f"N={n} box={box[0]:.4f} building context")
     def timed_run(pairs, warmup, steps):
         sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp32", shift="cutoff",
-                    max_nb=128, pairs=pairs)
+                    max_nb=128, pairs=pairs, rebuild=args.rebuild)
         state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
         torch.cuda.synchronize()
         log(f"pairs={pairs}: warmup {warmup} steps")
@@ -394,7 +399,7 @@ def main():
         if st != 0:
             raise SystemExit(f"warmup flagged status {st} flags {flags}")
         # events for every launch of the timed run are created here, not in it
-        C.mdpl_set_timing(sim.handle, True, reserve=steps + 8)
+        C.mdpl_set_timing(sim.handle, not args.no_kernel_timing, reserve=steps + 8)
         C.mdpl_kernel_time(sim.handle, 0)  # reset
         C.mdpl_kernel_time(sim.handle, 1)
         rb0 = sim.rebuild_stats()
@@ -440,9 +445,9 @@ def main():
         # per list entry its 16-bit tile offset (2)
         alg_bytes = n * (4 + 24 + 48 + 24) + 2 * entries
     avg_s = (f_ms / 1e3) / max(f_n, 1)
-    achieved = alg_bytes / avg_s / 1e9
+    achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else None
     traffic = measured_traffic() if args.pairs == "full" else None
-    flops = measured_flops(avg_s, entries) if args.pairs == "full" else None
+    flops = measured_flops(avg_s, entries) if args.pairs == "full" and avg_s > 0 else None
 
     out = {
         "metric": METRIC,
@@ -477,7 +482,7 @@ def main():
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": avg_s * 1e6,

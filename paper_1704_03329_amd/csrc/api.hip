@@ -89,12 +89,15 @@ struct mdpl_sim {
   double* last_row;        // device: thermo row of the last step of the last run
   bool last_row_valid;
   // rebuild rule of Eq. extended_cutoff
-  unsigned long long* vstep;
-  unsigned int* done;
+  double* vpart[2];        // per-workgroup largest |v|^2 of the last two drifting launches
+  int nvpart;              // capacity of each
   double* bound;
   KickRecord* ring_host;   // pinned, host-mapped
   KickRecord* ring_dev;
   KickTrack track;         // for the next drifting launch
+  int pend_n;              // workgroups of the last drifting launch, its record not yet published (0: none)
+  int64_t pend_step;       // the step index of that record
+  int track_cur;           // slot of the next drifting launch's maxima
   int64_t n_rebuilds, n_early, n_syncs;
 };
 
@@ -168,6 +171,13 @@ void lj_grid(const mdpl_lj_params* p, Grid* g, int* threads) {
   *threads = t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
 
+// Workgroups of any drifting launch: k_vv (256 particles each) or the fused
+// force pass (the brick order, at most nbricks + 16 entries).
+int64_t track_slots(int64_t n, const Grid& g) {
+  const int64_t a = div_up(n, 256), b = (int64_t)g.nbricks + 16;
+  return a > b ? a : b;
+}
+
 size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   const int64_t n = p->n;
   const int64_t npad = div_up(n, 256) * 256;
@@ -186,6 +196,7 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += align256(4 * (size_t)npad);             // cnt
   b += align256(4 * (size_t)(n + 1));          // offsets
   b += align256(8 * (size_t)(3 * nblk + 2));   // partials
+  b += 2 * align256(8 * (size_t)track_slots(n, g));  // the rule's per-workgroup maxima
   b += align256(256);                          // flags, maxcount, max_disp, pe_w_tmp, rule, last row
   b += align256(4 * 8 * (size_t)g.nbricks);   // brick order of the tile kernels
   return b;
@@ -396,6 +407,9 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
   s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
   s->partials = take<double>(w, 8 * (size_t)(3 * s->nblk + 2));
+  s->nvpart = (int)track_slots(n, s->g);
+  s->vpart[0] = take<double>(w, 8 * (size_t)s->nvpart);
+  s->vpart[1] = take<double>(w, 8 * (size_t)s->nvpart);
   char* small = take<char>(w, 256);
   {
     const std::vector<int32_t> order = brick_order(s->g);
@@ -413,8 +427,6 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->maxcount = (int32_t*)(small + 4);
   s->max_disp = (double*)(small + 8);
   s->pe_w_tmp = (double*)(small + 16);
-  s->vstep = (unsigned long long*)(small + 32);
-  s->done = (unsigned int*)(small + 40);
   s->bound = (double*)(small + 48);
   s->last_row = (double*)(small + 64);
   s->built = false;
@@ -444,7 +456,14 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
     }
     s->ring_host = (KickRecord*)h;
   }
-  s->track = KickTrack{s->vstep, s->done, s->bound, nullptr, 0, p->dt};
+  s->track = KickTrack{};
+  s->track.part[0] = s->vpart[0];
+  s->track.part[1] = s->vpart[1];
+  s->track.bound = s->bound;
+  s->track.dt = p->dt;
+  s->pend_n = 0;
+  s->pend_step = 0;
+  s->track_cur = 0;
   hipError_t e = hipMemsetAsync(small, 0, 256, s->st);
   if (e != hipSuccess) {
     g_last_hip_error = (int32_t)e;
@@ -686,6 +705,14 @@ mdpl_status rule_decide(mdpl_sim* s, bool* need) {
       return MDPL_OK;
     }
   }
+  if (s->pend_n > 0) {  // the record of step k is still pending: publish it now
+    KickTrack kt = s->track;
+    kt.cur = s->track_cur;
+    kt.pub_n = s->pend_n;
+    kt.pub_step = s->pend_step;
+    HIP_TRY(publish_record(kt, s->st));
+    s->pend_n = 0;
+  }
   HIP_TRY(hipStreamSynchronize(s->st));
   ++s->n_syncs;
   KickRecord rk;
@@ -762,6 +789,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
                                s->flags, s->maxcount, s->st));
     s->have_ref = true;
     s->have_list = !s->tl.cells;
+    s->pend_n = 0;  // bound restarts at zero with the new list
     s->kb = s->gstep;
     s->since = 0;
     ++s->n_rebuilds;
@@ -779,6 +807,21 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     spare[1] = t[1];
     spare[2] = t[2];
   };
+
+  // the rule's bookkeeping around every drifting launch (no-op without the rule)
+  auto arm = [&]() {
+    s->track.step = s->gstep + 1;
+    s->track.cur = s->track_cur;
+    s->track.pub_n = s->pend_n;
+    s->track.pub_step = s->pend_step;
+  };
+  auto drifted = [&](int groups) {
+    if (!s->track.ring) return;
+    s->pend_n = groups;
+    s->pend_step = s->track.step;
+    s->track_cur ^= 1;
+  };
+  const int force_groups = s->g.order ? s->g.norder : ((s->g.nbricks + 7) / 8) * 8;
 
   mdpl_status r = MDPL_OK;
   if (!cont) {
@@ -820,10 +863,11 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     if (!fused) {
       const bool ke = step > 1 && sampled(step - 1);
       int nb = 0;
-      s->track.step = s->gstep + 1;
+      arm();
       HIP_TRY(vv_step(cur.x, cur.y, cur.z, spare[0], spare[1], spare[2], cur.vx, cur.vy, cur.vz,
                       cur.fx, cur.fy, cur.fz, prec, n, h, dt, step == 1 ? 0 : 1, ke, s->partials,
                       s->flags, s->st, &nb, step == 1 ? nullptr : collide(step - 1), &s->track));
+      drifted(nb);
       swap_positions();
       if (ke) HIP_TRY(reduce_partials(s->partials, nb, 1, 1, row(step - 1), ke_scale, s->st));
     }
@@ -842,11 +886,14 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     const bool en = sampled(step);
     // the pass of the last step stores its forces for the final half kick
     fused = can_fuse && step < nsteps;
-    s->track.step = s->gstep + 1;
+    if (fused) arm();
     r = force(cur, en, en ? row(step) + 1 : nullptr, en ? 1 : 0, fused, spare,
               en ? row(step) : nullptr, en ? row(step) + 3 : nullptr);
     if (r != MDPL_OK) return r;
-    if (fused) swap_positions();
+    if (fused) {
+      drifted(force_groups);
+      swap_positions();
+    }
   }
   if (nsteps > 0) {
     const bool ke = sampled(nsteps);

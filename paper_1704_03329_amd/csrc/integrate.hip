@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256) void k_vv(const double* __restrict__ x,
                                             KickTrack kt) {
 #pragma clang fp contract(off)
   __shared__ double sh[4];
+  if (mode == 0 || mode == 1) kick_publish(kt, sh);
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double k = 0.0, m2 = 0.0;
   if (s < n) {
@@ -107,9 +108,20 @@ __global__ __launch_bounds__(256) void k_vv(const double* __restrict__ x,
     if (threadIdx.x == 0) ke_part[blockIdx.x] = t;
   }
   if (mode == 0 || mode == 1) {
-    const double mb = block_max256(m2, sh);  // NaN propagates as the largest bit pattern
-    if (threadIdx.x == 0) kick_track(kt, mb);
+    const double mb = block_max256(m2, sh);  // a NaN speed is caught by the non-finite flag
+    if (threadIdx.x == 0) kick_store(kt, mb);
   }
+}
+
+// The pending record of the rebuild rule, one workgroup (the host needs it now).
+__global__ __launch_bounds__(256) void k_publish(KickTrack kt) {
+  __shared__ double sh[4];
+  kick_publish(kt, sh);
+}
+
+hipError_t publish_record(const KickTrack& kt, hipStream_t st) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, st, kt);
+  return hipGetLastError();
 }
 
 hipError_t vv_step(const double* x, const double* y, const double* z, double* nx, double* ny,

@@ -114,11 +114,11 @@ hipError_t build_nlist(const double* sx, const double* sy, const double* sz,
 
 // Tiled neighbour list of the LJ path.  One workgroup per brick stages the
 // positions of the brick's (B+2)^3-cell neighbourhood (its "tile") in LDS;
-// an entry is the byte offset (8 x slot) of the neighbour's coordinate in a
-// tile array, 16 bits, packed four to a 64-bit word, the words
-// column-major: entry m of slot s is 16-bit lane (m & 3) of
-// nbr[(m >> 2) * stride + s].  The last word of a list is padded with the
-// offset of kTileDummy, a tile slot that holds a position far outside the box.
+// an entry is the neighbour's tile slot as a byte offset (below), 16 bits,
+// packed four to a 64-bit word, the words column-major: entry m of slot s
+// is 16-bit lane (m & 3) of nbr[(m >> 2) * stride + s].  The last word of a
+// list is padded with the offset of kTileDummy, a tile slot that holds a
+// position far outside the box.
 constexpr int kTileMax = 3072;              // tile slots (LDS)
 constexpr int kBrickMax = 1024;             // particles of one brick the list builder counts
 constexpr int kTileDummy = kTileMax - 1;    // padding slot
@@ -126,8 +126,9 @@ constexpr int kTileCap = kTileMax - 1;      // particles a tile can hold
 constexpr int kTileCells = 125;             // B <= 3 per axis
 constexpr int kTileMaxHalf = 2144;          // tile slots of a half-list tile (LDS)
 // A list entry is the partner's tile slot u as a byte offset: u << 4 in full
-// lists (the plain force pass reads the 16-byte x-y pair there and z at half
-// of it), u << 3 in half lists (8-byte arrays).
+// lists (the offset of the slot's 16-byte value in the FP32 force tile, of
+// its x-y pair in the FP64 one, and twice its offset in the 8-byte arrays),
+// u << 3 in half lists (8-byte arrays).
 constexpr int kFullShift = 4;
 constexpr int kHalfShift = 3;
 struct TileList {
@@ -153,14 +154,17 @@ struct LJConst {
   double box[3], half[3], inv_box[3];
 };
 
-// Rebuild rule of Eq. extended_cutoff: the kernel that drifts the positions
-// (the fused force pass or k_vv) records the largest speed of the step and
-// keeps bound = sum over the steps since the last build of dt * max|v|, an
-// upper bound of every particle's displacement since then.  The last
-// workgroup of the launch adds the step's term and publishes
-// {bound, max|v|} with the global step index in a ring of host-visible
+// Rebuild rule of Eq. extended_cutoff: every kernel that drifts the
+// positions (the fused force pass or k_vv) stores the largest |v|^2 of each
+// workgroup; workgroup 0 of the next drifting launch, when that launch has
+// ended, reduces them, adds dt * max|v| to bound (the sum over the steps
+// since the last build, an upper bound of every particle's displacement) and
+// publishes {bound, max|v|} with the step index in a ring of host-visible
 // records, so that the host can decide on a rebuild without waiting for the
-// stream.  The rebuild (k_reorder) sets bound back to zero.
+// stream.  No atomics and no device-scope fences are needed (the launch
+// boundary orders the maxima before their reduction).  The host publishes a
+// pending record with k_publish when it must decide at once; the rebuild
+// (k_reorder) sets bound back to zero and drops the pending record.
 struct KickRecord {
   int64_t stamp;  // global step index of the positions the drift produced (-1: empty)
   double bound;   // sum of dt * max|v| since the last build, this step included
@@ -169,33 +173,51 @@ struct KickRecord {
 };
 constexpr int kRing = 64;  // records kept (indexed by stamp mod kRing)
 struct KickTrack {
-  unsigned long long* vstep;  // device: bits of the step's largest |v|^2 (non-negative double)
-  unsigned int* done;         // device: workgroups of the launch that have finished
-  double* bound;              // device
-  KickRecord* ring;           // host-visible records (device address); null: no tracking
-  int64_t step;               // global step index of the positions produced
+  double* part[2];    // device: per-workgroup largest |v|^2 of the last two drifting launches
+  double* bound;      // device
+  KickRecord* ring;   // host-visible records (device address); null: no tracking
+  int64_t step;       // global step index of the positions this launch produces
+  int64_t pub_step;   // step index of the record to publish first
+  int pub_n;          // workgroups of the launch that produced it (0: none pending)
+  int cur;            // part[cur] takes this launch's maxima; part[cur ^ 1] holds the pending ones
   double dt;
 };
-// Called by one thread of every workgroup of a drifting launch with the
-// workgroup's largest |v|^2 (0 for a workgroup without particles).
-__device__ inline void kick_track(const KickTrack& kt, double m2) {
+// Thread 0 of every workgroup of a drifting launch: the workgroup's largest
+// |v|^2 (0 without particles; a non-finite value counts as infinite).
+__device__ inline void kick_store(const KickTrack& kt, double m2) {
   if (!kt.ring) return;
-  atomicMax(kt.vstep, (unsigned long long)__double_as_longlong(m2));
-  __threadfence();
-  const unsigned prev = atomicAdd(kt.done, 1u);
-  if (prev != gridDim.x - 1) return;
-  __threadfence();
-  const unsigned long long bits = atomicExch(kt.vstep, 0ull);
-  atomicExch(kt.done, 0u);
-  const double vmax = sqrt(__longlong_as_double((long long)bits));
-  const double b = *kt.bound + kt.dt * vmax;
-  *kt.bound = b;
-  KickRecord* r = kt.ring + (kt.step & (kRing - 1));
-  r->bound = b;
-  r->vmax = vmax;
-  __threadfence_system();
-  __hip_atomic_store(&r->stamp, kt.step, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  kt.part[kt.cur][blockIdx.x] = m2 >= 0.0 ? m2 : __builtin_huge_val();
 }
+// Every thread of workgroup 0 of a drifting launch, before its other work
+// (no-op elsewhere): the pending record.  sh: one double per wave.
+__device__ inline void kick_publish(const KickTrack& kt, double* sh) {
+  if (!kt.ring || kt.pub_n <= 0 || blockIdx.x != 0) return;
+  const double* p = kt.part[kt.cur ^ 1];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < kt.pub_n; i += blockDim.x) m = p[i] > m ? p[i] : m;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 1; w < nw; ++w) m = sh[w] > m ? sh[w] : m;
+    const double vmax = sqrt(m);
+    const double b = *kt.bound + kt.dt * vmax;
+    *kt.bound = b;
+    KickRecord* r = kt.ring + (kt.pub_step & (kRing - 1));
+    r->bound = b;
+    r->vmax = vmax;
+    __threadfence_system();
+    __hip_atomic_store(&r->stamp, kt.pub_step, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  __syncthreads();
+}
+// The pending record alone (one workgroup).
+hipError_t publish_record(const KickTrack& kt, hipStream_t st);
 
 struct ForceOut {
   void *fx, *fy, *fz;     // force arrays (float or double)

@@ -4,22 +4,26 @@
 // dr_ij = r_i - r_j (min image), summed over the neighbour list of i and
 // written once per particle (gather only, no atomics: the paper's choice of
 // looping over all ordered pairs and writing to the first particle, Sec. 2).
-// Each workgroup handles one brick of cells and stages the image positions of
-// its neighbourhood in LDS (tile.h): the plain pass keeps x and y of a slot
-// side by side and z apart, the energy pass three arrays.  A list entry is 16
-// times the partner's slot, the byte offset of its x-y pair; half of it
-// indexes the 8-byte arrays.  The cutoff test d2 < rc^2 uses the FP64 separation; the periodic
-// image is added to a tile position once, and the plain pass forms d2 with
-// fused multiply-adds, so a pair can be classified differently from the
-// definition only within a few units in the last place of rc^2.  The
-// energy pass uses the definition's uncontracted d2.
+// Each workgroup handles one brick of cells and stages its neighbourhood (the
+// tile, tile.h) in LDS; a list entry is 16 times the partner's tile slot.
 //
-// Precision (FP32 mode): the separation and the test in FP64, the pair force
-// factor in FP32 from the rounded squared distance, per-particle sums in
-// FP64 (cheaper than converting the three separations), stored as FP32.  Energy and
-// virial (sampled steps) are formed per pair in FP64 and reduced per block
-// with wavefront shuffles into FP64 partials; a single-block pass sums the
-// partials in a fixed order, so results are reproducible run to run.
+// FP32 mode (k_lj_force32): the tile holds FP32 coordinates relative to the
+// tile centre (one 16-byte gather per entry) and the whole pair loop is
+// FP32; pairs whose FP32 squared distance falls in a narrow band around rc^2
+// are classified by the FP64 test instead (see the derivation there).
+// Forces are stored as FP32.  Energy and virial (sampled steps) are formed
+// per pair in FP64 from the FP64 image positions and reduced per block with
+// wavefront shuffles into FP64 partials; a single-block pass sums the
+// partials in a fixed order, so results are reproducible run to run.  The
+// energy pass computes its forces with the plain pass's FP32 arithmetic, so
+// sampling a step leaves the trajectory unchanged.
+//
+// FP64 mode (k_lj_force<double, ...>): FP64 image positions in the tile, the
+// uncontracted squared distance of the definition, the reciprocal by
+// estimate and Newton steps; the plain and the energy pass share the pair
+// arithmetic.  The cutoff test uses the FP64 separation of the image
+// positions, so a pair can be classified differently from the definition
+// only within a few units in the last place of rc^2.
 //
 // Potential energy: PE = 1/2 sum over ordered pairs (each unordered pair
 // once), e_i = 1/2 sum_j V(r_ij); virial W = 1/2 sum over ordered pairs of
@@ -58,6 +62,29 @@ __device__ __forceinline__ double fused_kick(const ForceOut& out, int64_t s, dou
   return k;
 }
 
+// FP64 pair arithmetic of the FP64 passes and of the energy and virial of
+// every pass (one definition, so that the plain and the energy pass of the
+// FP64 mode give the same forces): the reciprocal of d2 by the hardware
+// estimate and two Newton steps (a few ulp), s6 = (s^2/d2)^3 and the force
+// factor f/dr = 48 eps s6 (s6 - 1/2) / d2.
+__device__ __forceinline__ double lj_inv64(double d2) {
+#pragma clang fp contract(off)
+  double inv = __builtin_amdgcn_rcp(d2);
+  inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
+  inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
+  return inv;
+}
+__device__ __forceinline__ double lj_g64(double inv, const LJConst& c, double& s6) {
+#pragma clang fp contract(off)
+  const double s2 = c.sigma2 * inv;
+  s6 = s2 * s2 * s2;
+  return 48.0 * c.eps * inv * s6 * (s6 - 0.5);
+}
+__device__ __forceinline__ double lj_v64(double s6, const LJConst& c) {
+#pragma clang fp contract(off)
+  return 4.0 * c.eps * (s6 * s6 - s6) + c.shift_v;
+}
+
 // Largest |v|^2 of the workgroup (v2 per thread, 0 where none) to the rule's
 // tracking; one barrier.
 __device__ __forceinline__ void block_track(const KickTrack& kt, double v2, double* sh) {
@@ -72,7 +99,7 @@ __device__ __forceinline__ void block_track(const KickTrack& kt, double v2, doub
     const int nw = (blockDim.x + 63) >> 6;
     double m = sh[0];
     for (int k = 1; k < nw; ++k) m = sh[k] > m ? sh[k] : m;
-    kick_track(kt, m);
+    kick_store(kt, m);
   }
 }
 
@@ -94,9 +121,10 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
   __shared__ Tile t;
   __shared__ double red[48];  // up to 16 waves: e, w, ke
   __shared__ double vred[16];
+  if (out.fuse) kick_publish(out.track, vred);
   const int brick = brick_of_block(g);
-  if (brick >= g.nbricks) {  // padding workgroup: still counted by the rule's tracking
-    if (out.fuse && threadIdx.x == 0) kick_track(out.track, 0.0);
+  if (brick >= g.nbricks) {  // padding workgroup: its (empty) maximum still goes to the rule
+    if (out.fuse && threadIdx.x == 0) kick_store(out.track, 0.0);
     return;
   }
   const int total = tile_cells(g, brick, cs, t);
@@ -160,31 +188,24 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
           // pair energy and virial in FP64 on the sampled steps
           const double d2 = sq_sum(dx, dy, dz);
           const bool in = d2 < c.rc2;
-          // reciprocal: hardware estimate and two Newton steps (a few ulp)
-          double inv = __builtin_amdgcn_rcp(d2);
-          inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
-          inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
-          const double s2 = c.sigma2 * inv;
-          const double s6 = s2 * s2 * s2;
-          const double gg = 48.0 * c.eps * inv * s6 * (s6 - 0.5);
-          const double v = 4.0 * c.eps * (s6 * s6 - s6) + c.shift_v;
+          double s6;
+          const double gg = lj_g64(lj_inv64(d2), c, s6);
           g = in ? gg : 0.0;
-          ei += in ? 0.5 * v : 0.0;
+          ei += in ? 0.5 * lj_v64(s6, c) : 0.0;
           w += 0.5 * g * d2;
+        } else if constexpr (sizeof(MT) == 8) {
+          // the energy pass's force factor (same operations)
+          const double d2 = sq_sum(dx, dy, dz);
+          double s6;
+          const double gg = lj_g64(lj_inv64(d2), c, s6);
+          g = d2 < c.rc2 ? gg : 0.0;
         } else {
           const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
           const bool in = d2 < c.rc2;
-          MT inv;
-          if constexpr (sizeof(MT) == 4) {
-            // outside the cutoff the reciprocal of FLT_MAX drives the factor to zero
-            inv = __builtin_amdgcn_rcpf(in ? (float)d2 : 3.0e38f);
-          } else {
-            inv = 1.0 / d2;
-          }
+          // outside the cutoff the reciprocal of FLT_MAX drives the factor to zero
+          const MT inv = __builtin_amdgcn_rcpf(in ? (float)d2 : 3.0e38f);
           const MT x2 = inv * inv;
-          MT gg = (x2 * x2) * (fa * (x2 * inv) - fb);
-          if constexpr (sizeof(MT) != 4) gg = in ? gg : (MT)0;
-          g = (double)gg;
+          g = (double)((x2 * x2) * (fa * (x2 * inv) - fb));
         }
         ax = __builtin_fma(g, dx, ax);
         ay = __builtin_fma(g, dy, ay);
@@ -254,6 +275,287 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
   }
 }
 
+// ------------------------------------------------------------ FP32 path
+// Pair forces of the FP32 precision mode from FP32 coordinates relative to
+// the centre of the brick's tile: X = fl32((x + k L) - o), |X| below
+// (B/2 + 1) cell sides.  A pair's separation is the FP32 difference of two
+// such values, so the pair loop needs no FP64 arithmetic: one 16-byte LDS
+// gather, three FP32 differences, the squared distance, the reciprocal and
+// the force factor x^4 (A x^3 - B), x = 1/d2, accumulated in FP32.
+//
+// Cutoff classification.  The FP32 squared distance d2f of a pair is within
+// e of the FP64 one formed from the image positions (bound derived in
+// lj_force32_band), so d2f < rc^2 - band and d2f >= rc^2 + band decide the
+// pair as the FP64 test would.  A particle with an entry between the two
+// (about one in a thousand) walks its list again with the exact rule: for
+// such entries the FP64 test on the image separation, the same as in the
+// energy pass.  Both passes therefore include the same pairs and, sharing
+// the FP32 force arithmetic and the order of the sums, give bit-identical
+// forces: a sampled step does not perturb the trajectory.
+struct F32Const {
+  float fa, fb;      // 48 eps s^12, 24 eps s^6
+  float r2lo, r2hi;  // rc^2 -/+ band, rounded outward
+};
+
+// FP32 force factor f/dr of a pair: in selects the pair (the reciprocal of
+// FLT_MAX drives the factor of an excluded pair to zero).
+__device__ __forceinline__ float lj_g32(float d2f, bool in, const F32Const& k) {
+#pragma clang fp contract(off)
+  const float inv = __builtin_amdgcn_rcpf(in ? d2f : 3.0e38f);
+  const float x2 = inv * inv;
+  return (x2 * x2) * __builtin_fmaf(k.fa, x2 * inv, -k.fb);
+}
+
+__device__ __forceinline__ float d2_32(float dx, float dy, float dz) {
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+// FP64 squared distance of the exact rule: the particle's stored position
+// minus the image position of the partner (the energy pass forms it from
+// the same values).
+__device__ __forceinline__ double d2_image(double xs, double ys, double zs, double qx, double qy,
+                                           double qz) {
+  return sq_sum(xs - qx, ys - qy, zs - qz);
+}
+
+// FP64 image position of tile slot u (the slot map gives its cell).
+template <typename TS>
+__device__ __forceinline__ void slot_image(const TS& t, const Grid& g, const double* __restrict__ x,
+                                           const double* __restrict__ y,
+                                           const double* __restrict__ z, int u, double& qx,
+                                           double& qy, double& qz) {
+  const int lo = t.cell[u];
+  const int src = t.src[lo] + (u - t.prefix[lo]);
+  const int code = t.code[lo];
+  qx = image_coord(x[src], code & 3, g.box[0]);
+  qy = image_coord(y[src], (code >> 2) & 3, g.box[1]);
+  qz = image_coord(z[src], (code >> 4) & 3, g.box[2]);
+}
+
+// One workgroup per brick, two lanes per particle (each takes every other
+// list word; their sums are added by one exchange).  The plain pass stages
+// the FP32 tile; the energy pass stages the FP64 image positions (its
+// energy and virial are FP64 per pair) and forms the FP32 coordinates of
+// each partner from them with the same conversion as the plain tile load.
+template <typename OT, bool ENERGY>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+void k_lj_force32(const double* __restrict__ x, const double* __restrict__ y,
+                  const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g,
+                  TileList tl, LJConst c, F32Const k, ForceOut out) {
+  using Tile = std::conditional_t<ENERGY, TileShared, TileF4>;
+  __shared__ Tile t;
+  __shared__ double red[48];  // up to 16 waves: e, w, ke
+  __shared__ double vred[16];
+  if (out.fuse) kick_publish(out.track, vred);
+  const int brick = brick_of_block(g);
+  if (brick >= g.nbricks) {  // padding workgroup: its (empty) maximum still goes to the rule
+    if (out.fuse && threadIdx.x == 0) kick_store(out.track, 0.0);
+    return;
+  }
+  const int total = tile_cells(g, brick, cs, t);
+  double ox, oy, oz;
+  tile_centre(g, brick, ox, oy, oz);
+  if constexpr (ENERGY) tile_load<true>(g, x, y, z, total, t);
+  else tile_load_f4(g, x, y, z, total, ox, oy, oz, t);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  double scale = out.scale;
+  if (out.scale_dev) scale *= *out.scale_dev;
+  double e = 0.0, w = 0.0, ke = 0.0, vmax2 = 0.0;
+  constexpr int LPP = 2;
+  const int part = (int)threadIdx.x % LPP;
+  for (int s = s0 + (int)threadIdx.x / LPP; s < s1; s += (int)blockDim.x / LPP) {
+    // the plain pass keeps only FP32 values live across the pair loop; the
+    // FP64 position is loaded again where it is needed (redo, kick)
+    float xi, yi, zi;
+    double xs = 0.0, ys = 0.0, zs = 0.0;
+    if constexpr (ENERGY) {
+      xs = x[s];
+      ys = y[s];
+      zs = z[s];
+      xi = rel32(xs, ox);
+      yi = rel32(ys, oy);
+      zi = rel32(zs, oz);
+    } else {
+      xi = rel32(x[s], ox);
+      yi = rel32(y[s], oy);
+      zi = rel32(z[s], oz);
+    }
+    const int ngroups = (tl.cnt[s] + 3) >> 2;
+    const uint64_t* __restrict__ col = tl.nbr + s;
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    double ei = 0.0;
+    bool band = false;
+    uint64_t next = part < ngroups ? col[(int64_t)part * tl.stride] : 0;
+    for (int gi = part; gi < ngroups; gi += LPP) {
+      const uint64_t word = next;
+      if (gi + LPP < ngroups) next = col[(int64_t)(gi + LPP) * tl.stride];
+      if constexpr (ENERGY) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          // entry: 16 x the partner's slot; half of it in the 8-byte arrays
+          const unsigned off8 = ((unsigned)(word >> (16 * m)) & 0xffffu) >> 1;
+          const double qx = *(const double*)((const char*)t.x + off8);
+          const double qy = *(const double*)((const char*)t.y + off8);
+          const double qz = *(const double*)((const char*)t.z + off8);
+          const float dx = xi - rel32(qx, ox);
+          const float dy = yi - rel32(qy, oy);
+          const float dz = zi - rel32(qz, oz);
+          const float d2f = d2_32(dx, dy, dz);
+          const double d2 = d2_image(xs, ys, zs, qx, qy, qz);
+          const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
+          const bool in = lo != hi ? d2 < c.rc2 : lo;
+          // pair energy and virial in FP64
+          double s6;
+          const double gg = lj_g64(lj_inv64(d2), c, s6);
+          ei += in ? 0.5 * lj_v64(s6, c) : 0.0;
+          w += in ? 0.5 * gg * d2 : 0.0;
+          const float gf = lj_g32(d2f, in, k);
+          ax = __builtin_fmaf(gf, dx, ax);
+          ay = __builtin_fmaf(gf, dy, ay);
+          az = __builtin_fmaf(gf, dz, az);
+        }
+      } else {
+        // the word's four partners are read before any is used
+        float4 q[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          q[m] = *(const float4*)((const char*)t.p + ((unsigned)(word >> (16 * m)) & 0xffffu));
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const float dx = xi - q[m].x, dy = yi - q[m].y, dz = zi - q[m].z;
+          const float d2f = d2_32(dx, dy, dz);
+          const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
+          band |= lo != hi;
+          const float gf = lj_g32(d2f, lo, k);
+          ax = __builtin_fmaf(gf, dx, ax);
+          ay = __builtin_fmaf(gf, dy, ay);
+          az = __builtin_fmaf(gf, dz, az);
+        }
+      }
+    }
+    if constexpr (!ENERGY) {
+      // an entry in the band: both lanes of the particle walk again with the exact rule
+      bool redo = band;
+      if (LPP == 2) redo = redo || __shfl_xor((int)band, 1, 64) != 0;
+      if (redo) {
+        const double xr = x[s], yr = y[s], zr = z[s];
+        ax = ay = az = 0.0f;
+        for (int gi = part; gi < ngroups; gi += LPP) {
+          const uint64_t word = col[(int64_t)gi * tl.stride];
+          for (int m = 0; m < 4; ++m) {
+            const unsigned u = (unsigned)(word >> (16 * m + kFullShift)) & 0xfffu;
+            const float4 q = t.p[u];
+            const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+            const float d2f = d2_32(dx, dy, dz);
+            const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
+            bool in = lo;
+            if (lo != hi && u != (unsigned)Tile::kDummy) {
+              double qx, qy, qz;
+              slot_image(t, g, x, y, z, (int)u, qx, qy, qz);
+              in = d2_image(xr, yr, zr, qx, qy, qz) < c.rc2;
+            }
+            const float gf = lj_g32(d2f, in, k);
+            ax = __builtin_fmaf(gf, dx, ax);
+            ay = __builtin_fmaf(gf, dy, ay);
+            az = __builtin_fmaf(gf, dz, az);
+          }
+        }
+      }
+    }
+    if (LPP == 2) {
+      ax += __shfl_xor(ax, 1, 64);
+      ay += __shfl_xor(ay, 1, 64);
+      az += __shfl_xor(az, 1, 64);
+      if (ENERGY) ei += __shfl_xor(ei, 1, 64);
+      if (part) continue;
+    }
+    if (out.fuse) {
+      if constexpr (!ENERGY) {
+        xs = x[s];
+        ys = y[s];
+        zs = z[s];
+      }
+      // the kicks use the force as stored (rounded to OT), like k_vv
+      double m2;
+      ke += fused_kick(out, s, xs, ys, zs, out.vx[s], out.vy[s], out.vz[s],
+                       (double)(OT)((double)ax * scale), (double)(OT)((double)ay * scale),
+                       (double)(OT)((double)az * scale), m2);
+      vmax2 = m2 > vmax2 ? m2 : vmax2;
+      if (ENERGY) e += ei;
+      continue;
+    }
+    const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
+    ((OT*)out.fx)[o] = (OT)((double)ax * scale);
+    ((OT*)out.fy)[o] = (OT)((double)ay * scale);
+    ((OT*)out.fz)[o] = (OT)((double)az * scale);
+    if (ENERGY) {
+      if (out.e_atom) out.e_atom[o] = ei;
+      e += ei;
+    }
+  }
+  if (out.fuse && out.track.ring) block_track(out.track, vmax2, vred);
+  if (ENERGY) {
+    e = wave_sum(e);
+    w = wave_sum(w);
+    ke = wave_sum(ke);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[wave] = e;
+      red[16 + wave] = w;
+      red[32 + wave] = ke;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nw = (blockDim.x + 63) >> 6;
+      double pe = 0.0, ww = 0.0, kk = 0.0;
+      for (int q = 0; q < nw; ++q) {
+        pe += red[q];
+        ww += red[16 + q];
+        kk += red[32 + q];
+      }
+      if (out.fuse) {
+        out.partials[3 * brick] = pe;
+        out.partials[3 * brick + 1] = ww;
+        out.partials[3 * brick + 2] = kk;
+      } else {
+        out.partials[2 * brick] = pe;
+        out.partials[2 * brick + 1] = ww;
+      }
+    }
+  }
+}
+
+// The band of the FP32 classification.  A tile coordinate |X| < M = 2^p
+// (M above (B/2 + 1) cell sides) is within 2^(p-25) of its FP64 value
+// (whose own rounding, ~1e-14, is covered by the factor below); an FP32
+// difference of a pair near the cutoff, below rc (1 + e) <= 2^q, is rounded
+// within 2^(q-25).  So
+// each separation component is within D = 2^(p-24) + 2^(q-25) of the FP64
+// one, and the FP32 squared distance of a pair near the cutoff within
+// e = 2 sqrt(3) rc D + 3 D^2 + 3 2^-24 rc^2 (three rounded operations).  The
+// band is 4 e.
+static F32Const f32_const(const Grid& g, const LJConst& c) {
+  F32Const k;
+  const double sig6 = c.sigma2 * c.sigma2 * c.sigma2;
+  k.fa = (float)(48.0 * c.eps * sig6 * sig6);
+  k.fb = (float)(24.0 * c.eps * sig6);
+  double m = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double h = (0.5 * g.B[a] + 1.0) * (g.box[a] / g.nc[a]);
+    m = h > m ? h : m;
+  }
+  const double ulp = 1.0 / 16777216.0;  // 2^-24
+  const double pm = exp2(ceil(log2(m * (1.0 + 1e-9))));
+  const double rc = sqrt(c.rc2);
+  const double pr = exp2(ceil(log2(rc * (1.0 + 1e-6))));
+  const double d = pm * ulp + 0.5 * pr * ulp;
+  const double err = 2.0 * sqrt(3.0) * rc * d + 3.0 * d * d + 3.0 * ulp * c.rc2;
+  const double band = 4.0 * err;
+  k.r2lo = nextafterf((float)(c.rc2 - band), 0.0f);
+  k.r2hi = nextafterf((float)(c.rc2 + band), 3.0e38f);
+  return k;
+}
+
 template <typename MT, typename OT>
 static void launch_force(bool energy, hipStream_t st, const double* x, const double* y,
                          const double* z, const int32_t* cs, const Grid& g, const TileList& tl,
@@ -280,9 +582,18 @@ hipError_t lj_force(const double* x, const double* y, const double* z, const int
     case 2:
       launch_force<double, double>(energy, st, x, y, z, cell_start, g, tl, c, out);
       break;
-    case 1:
-      launch_force<float, float>(energy, st, x, y, z, cell_start, g, tl, c, out);
+    case 1: {
+      const F32Const k = f32_const(g, c);
+      const dim3 grid(tile_grid(g));
+      const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
+      if (energy)
+        hipLaunchKernelGGL((k_lj_force32<float, true>), grid, dim3(two), 0, st, x, y, z, cell_start,
+                           g, tl, c, k, out);
+      else
+        hipLaunchKernelGGL((k_lj_force32<float, false>), grid, dim3(two), 0, st, x, y, z,
+                           cell_start, g, tl, c, k, out);
       break;
+    }
     default:
       launch_force<float, double>(energy, st, x, y, z, cell_start, g, tl, c, out);
       break;

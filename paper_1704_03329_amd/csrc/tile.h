@@ -56,6 +56,19 @@ struct TileXYOf {
   int code[kTileCells];
   uint8_t cell[CAP];
 };
+// FP32 force pass: x, y, z of a slot relative to the tile centre in one
+// 16-byte value; a full-list entry (16 x slot) is its byte offset
+template <int CAP>
+struct TileF4Of {
+  static constexpr int kSlots = CAP;
+  static constexpr int kDummy = CAP - 1;
+  static constexpr int kCap = CAP - 1;
+  float4 p[CAP];
+  int prefix[kTileCells + 1];
+  int src[kTileCells];
+  int code[kTileCells];
+  uint8_t cell[CAP];
+};
 // the cell table alone (kernels that map tile indices to slots only)
 struct TileCells {
   int prefix[kTileCells + 1];
@@ -70,6 +83,7 @@ using TileShared32 = TileOf<float, kTileMax>;
 using TileHalf = TileOf<double, kTileMaxHalf>;
 using TileHalf32 = TileOf<float, kTileMaxHalf>;
 using TileXY = TileXYOf<kTileMax>;
+using TileF4 = TileF4Of<kTileMax>;
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // run of bricks (a slab of the box) so that tile reloads hit its own L2.
@@ -206,6 +220,49 @@ __device__ inline void tile_load_xy(const Grid& g, const double* __restrict__ x,
     t.xy[u] = make_double2(x[src] + (double)((code & 3) - 1) * g.box[0],
                            y[src] + (double)(((code >> 2) & 3) - 1) * g.box[1]);
     t.z[u] = z[src] + (double)(((code >> 4) & 3) - 1) * g.box[2];
+  }
+  __syncthreads();
+}
+
+// Image position of a stored coordinate: x + k L with k = -1, 0, +1 from a
+// tile cell's code (the product is exact, so contraction cannot change it).
+__device__ __forceinline__ double image_coord(double x, int k, double L) {
+  return x + (double)(k - 1) * L;
+}
+
+// Centre of a brick's tile (the middle of the brick's B cells per axis), the
+// origin of the FP32 coordinates of the force pass.
+__device__ __forceinline__ void tile_centre(const Grid& g, int brick, double& ox, double& oy,
+                                            double& oz) {
+  int bx, by, bz;
+  brick_coords(g, brick, bx, by, bz);
+  ox = ((double)(bx * g.B[0]) + 0.5 * (double)g.B[0]) * (g.box[0] / (double)g.nc[0]);
+  oy = ((double)(by * g.B[1]) + 0.5 * (double)g.B[1]) * (g.box[1] / (double)g.nc[1]);
+  oz = ((double)(bz * g.B[2]) + 0.5 * (double)g.B[2]) * (g.box[2] / (double)g.nc[2]);
+}
+
+// FP32 coordinate of an image position relative to the tile centre.
+__device__ __forceinline__ float rel32(double image, double o) { return (float)(image - o); }
+
+// tile_load for the FP32 tile: rel32 of the image positions.  Ends with a
+// barrier.
+template <int CAP>
+__device__ inline void tile_load_f4(const Grid& g, const double* __restrict__ x,
+                                    const double* __restrict__ y, const double* __restrict__ z,
+                                    int total, double ox, double oy, double oz,
+                                    TileF4Of<CAP>& t) {
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int nt = total < TileF4Of<CAP>::kCap ? total : TileF4Of<CAP>::kCap;
+  tile_slot_cells(ntc, total, t);
+  if (threadIdx.x == 0)  // padding slot: no pair with it is ever inside the cutoff
+    t.p[TileF4Of<CAP>::kDummy] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+    const int lo = t.cell[u];
+    const int src = t.src[lo] + (u - t.prefix[lo]);
+    const int code = t.code[lo];
+    t.p[u] = make_float4(rel32(image_coord(x[src], code & 3, g.box[0]), ox),
+                         rel32(image_coord(y[src], (code >> 2) & 3, g.box[1]), oy),
+                         rel32(image_coord(z[src], (code >> 4) & 3, g.box[2]), oz), 0.0f);
   }
   __syncthreads();
 }

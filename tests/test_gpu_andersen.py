@@ -80,14 +80,18 @@ def test_zero_rate_is_plain_run_and_split_runs_continue():
     torch.cuda.synchronize()
     for k in c:
         assert torch.equal(c[k], e[k]), k
-    # continued runs (no rebinning or F(r0) pass between them), split inside a reuse period
+    # continued runs (no rebinning or F(r0) pass between them), split inside a
+    # reuse period, against one run with the same (absent) energy sampling
+    s5 = mk()
+    g = s5.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    s5.run(g, 40, 0, andersen=dict(th, step0=0))
     s4 = mk()
     f = s4.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
     s4.run(f, 17, 0, andersen=dict(th, step0=0))
     s4.run(f, 23, 0, andersen=dict(th, step0=17), cont=True)
     torch.cuda.synchronize()
-    for k in c:
-        assert torch.equal(c[k], f[k]), k
+    for k in g:
+        assert torch.equal(g[k], f[k]), k
 
 
 def test_bath_temperature_reached():

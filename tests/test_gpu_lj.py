@@ -123,6 +123,77 @@ def test_forces_after_motion_within_skin():
     assert abs(pe_w[0].item() - ref["pe"]) <= 1e-12 * abs(ref["pe"])
 
 
+def test_fp32_cutoff_band_classified_exactly():
+    """FP32 mode: pairs whose FP32 squared distance lands within the band
+    around rc^2 are classified by the FP64 test.  Isolated pairs planted at
+    rc (1 +/- d), d down to 1e-8, carry the force at the cutoff (0.039) or
+    nothing, exactly as the oracle's FP64 test decides; the energy pass
+    gives the same forces bit for bit."""
+    r = mdinputs.rng(31)
+    base = (np.stack(np.meshgrid(*[np.arange(4)] * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5) * 6.0
+    base = base + r.normal(0.0, 0.3, base.shape)
+    u = r.normal(size=base.shape)
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    deltas = np.array([-1e-8, 1e-8, -1e-7, 1e-7, -5e-7, 5e-7, -2e-6, 2e-6, -1e-5, 1e-5, -1e-3, 1e-3])
+    dist = 2.5 * (1.0 + deltas[np.arange(base.shape[0]) % deltas.size])
+    pos = np.concatenate([base, base + dist[:, None] * u])
+    box = np.array([24.0, 24.0, 24.0])
+    pos = olj.wrap(pos, box)
+    ref = olj.lj_forces(pos, box, 2.5)
+    inside = np.linalg.norm(ref["F"], axis=1) > 0
+    assert 0 < inside.sum() < pos.shape[0]  # both sides of the cutoff are planted
+    sim = _sim(pos.shape[0], box, rc=2.5, skin=0.3, precision="fp32", max_nb=64)
+    x, y, z = split_dev(pos)
+    sim.build(x, y, z)
+    fx, fy, fz, _, _ = sim.forces(x, y, z)
+    F = torch.stack([fx, fy, fz], 1).double().cpu().numpy()
+    err = np.linalg.norm(F - ref["F"], axis=1)
+    assert np.max(err) <= 1e-5 * np.max(np.linalg.norm(ref["F"], axis=1)), np.max(err)
+    ex, ey, ez, _, _ = sim.forces(x, y, z, energy=True)
+    for a, b in ((fx, ex), (fy, ey), (fz, ez)):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sampling_leaves_trajectory_unchanged(precision):
+    """The energy pass of a sampled step computes its forces with the plain
+    pass's arithmetic: runs that sample every 5 steps and never give the
+    same state bit for bit."""
+    d = mdinputs.lj_fluid(10, temperature=1.0, seed=5)
+    box = d["box"]
+    mk = lambda: _sim(1000, box, rc=2.5, skin=0.3, reuse_every=10, precision=precision)
+    a, _ = _run(mk(), d["pos"], d["vel"], 30, 5)
+    b, _ = _run(mk(), d["pos"], d["vel"], 30, 0)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_fp32_forces_melted_fluid_every_atom():
+    """FP32 forces on every atom of a melted fluid (8000 atoms at rho 0.8442,
+    1500 FP64 steps at T* = 1 from the lattice) against the FP64 oracle."""
+    d = mdinputs.lj_fluid(20, temperature=1.0, seed=12)
+    box = d["box"]
+    n = d["pos"].shape[0]
+    md = _sim(n, box, rc=2.5, skin=0.3, dt=0.004, reuse_every=5, precision="fp64", shift="cutoff")
+    state, _ = _run(md, d["pos"], d["vel"], 1500, 0)
+    assert md.check(raise_on_error=False)[0] == 0
+    pos, _, _ = _unpermute(state)
+    sim = _sim(n, box, rc=2.5, skin=0.3, precision="fp32", max_nb=128)
+    x, y, z = split_dev(pos)
+    sim.build(x, y, z)
+    fx, fy, fz, pe_w, _ = sim.forces(x, y, z, energy=True)
+    F = torch.stack([fx, fy, fz], 1).double().cpu().numpy()
+    ref = olj.lj_forces(pos, box, 2.5)
+    g, m = force_errors(F, ref["F"])
+    from paper_1704_03329_amd import mdpl as C
+
+    print(f"melted fluid: {C.mdpl_nlist_entries(sim.handle) / n:.2f} entries per atom, global {g:.2e}, "
+          f"per-atom {m:.2e}")
+    assert g <= 1e-5 and m <= 1e-5, (g, m)
+    assert abs(pe_w[0].item() - ref["pe"]) <= 1e-9 * abs(ref["pe"])
+    assert abs(pe_w[1].item() - ref["w"]) <= 1e-9 * abs(ref["w"])
+
+
 def test_capacity_overflow_flagged():
     from paper_1704_03329_amd import mdpl as C
 
@@ -259,13 +330,16 @@ def test_run_continue_bitwise():
     # rows of steps 30 and 40 come from the same passes as in the long run
     assert torch.equal(t2[1:], t1[3:])
     assert t2.shape == (3, 4)
+    # blocks that end inside reuse periods, against one run with the same
+    # (absent) energy sampling
+    s0, _ = _run(mk(), d["pos"], d["vel"], 40, 0)
     sim = mk()
     state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
     for block in (13, 1, 19, 7):
         sim.run(state, block, 0, cont=block != 13)
     torch.cuda.synchronize()
     for k in keys:
-        assert torch.equal(state[k], s1[k]), k
+        assert torch.equal(state[k], s0[k]), k
     assert sim.rebuild_stats()[0] == 1 + 4  # the initial build and steps 10, 20, 30, 40
     # other arrays, or a standalone build in between: no state to continue
     other = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
