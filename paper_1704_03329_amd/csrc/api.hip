@@ -194,6 +194,7 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += 3 * align256(8 * (size_t)n);            // px..
   b += align256(2 * (size_t)((p->max_nb + 3) & ~3) * (size_t)npad);  // nbr (16-bit tile indices)
   b += align256(4 * (size_t)npad);             // cnt
+  b += align256(4 * (size_t)kTabInts * (size_t)g.nbricks);  // tile tables
   b += align256(4 * (size_t)(n + 1));          // offsets
   b += align256(8 * (size_t)(3 * nblk + 2));   // partials
   b += 2 * align256(8 * (size_t)track_slots(n, g));  // the rule's per-workgroup maxima
@@ -399,6 +400,7 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   const int max_nb4 = (p->max_nb + 3) & ~3;
   s->tl.nbr = take<uint64_t>(w, 2 * (size_t)max_nb4 * (size_t)s->npad);
   s->tl.cnt = take<int32_t>(w, 4 * (size_t)s->npad);
+  s->tl.tab = take<int32_t>(w, 4 * (size_t)kTabInts * (size_t)s->g.nbricks);
   s->tl.stride = s->npad;
   s->tl.max_nb = p->max_nb;
   s->tl.half = p->pairs == MDPL_PAIRS_HALF;

@@ -125,15 +125,19 @@ constexpr int kTileDummy = kTileMax - 1;    // padding slot
 constexpr int kTileCap = kTileMax - 1;      // particles a tile can hold
 constexpr int kTileCells = 125;             // B <= 3 per axis
 constexpr int kTileMaxHalf = 2144;          // tile slots of a half-list tile (LDS)
-// A list entry is the partner's tile slot u as a byte offset: u << 4 in full
-// lists (the offset of the slot's 16-byte value in the FP32 force tile, of
-// its x-y pair in the FP64 one, and twice its offset in the 8-byte arrays),
-// u << 3 in half lists (8-byte arrays).
-constexpr int kFullShift = 4;
+// A list entry is the partner's tile slot u as a byte offset: u << 2 in full
+// lists (its offset in the 4-byte arrays of the FP32 force tile; the FP64
+// kernels scale it), u << 3 in half lists (8-byte arrays).
+constexpr int kFullShift = 2;
 constexpr int kHalfShift = 3;
+// Per-brick tile tables of the full lists (prefix, src, code of tile.h),
+// written by the list build for the force pass, which then need not derive
+// them every step: kTabInts ints per brick.
+constexpr int kTabInts = (kTileCells + 1) + 2 * kTileCells;
 struct TileList {
   uint64_t* nbr;
   int32_t* cnt;     // clamped to max_nb
+  int32_t* tab;     // nbricks * kTabInts (full lists; null: not kept)
   int64_t stride;   // words per group row (>= n)
   int max_nb;       // multiple of 4
   int threads;      // workgroup size of the tile kernels

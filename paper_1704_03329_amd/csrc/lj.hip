@@ -163,10 +163,10 @@ void k_lj_force(const double* __restrict__ x, const double* __restrict__ y,
       constexpr bool kAhead = !ENERGY && sizeof(MT) == 4;
       double qx, qy, qz;
       auto tile_pos = [&](int k) {
-        // entry: the slot's byte offset in the 16-byte x-y pairs; half of it
-        // in the 8-byte arrays
-        const unsigned off = (unsigned)(word >> (16 * k)) & 0xffffu;
-        const unsigned off8 = (unsigned)(word >> (16 * k + 1)) & 0x7fffu;
+        // entry: 4 x the slot; the byte offset in the 16-byte x-y pairs is
+        // four times it, in the 8-byte arrays twice
+        const unsigned e = (unsigned)(word >> (16 * k)) & 0xffffu;
+        const unsigned off = e << 2, off8 = e << 1;
         if constexpr (ENERGY) {
           qx = *(const double*)((const char*)t.x + off8);
           qy = *(const double*)((const char*)t.y + off8);
@@ -332,19 +332,53 @@ __device__ __forceinline__ void slot_image(const TS& t, const Grid& g, const dou
   qz = image_coord(z[src], (code >> 4) & 3, g.box[2]);
 }
 
-// One workgroup per brick, two lanes per particle (each takes every other
-// list word; their sums are added by one exchange).  The plain pass stages
-// the FP32 tile; the energy pass stages the FP64 image positions (its
-// energy and virial are FP64 per pair) and forms the FP32 coordinates of
-// each partner from them with the same conversion as the plain tile load.
-template <typename OT, bool ENERGY>
+// Lane groups of the FP32 pair loops, shared by the plain and the energy
+// pass so that both sum a particle's pairs in the same order.  The brick's
+// particles are taken in passes of blockDim/2 with two lanes each; a last,
+// partial pass of m particles gives each T lanes, T the largest power of two
+// up to 16 with m T <= blockDim, so that a few leftover particles do not hold
+// the workgroup for a whole pass.  Lane p of a group takes the list words
+// p, p + T, p + 2T, ...; the group's sums are combined by butterflies.
+struct LaneGroup {
+  int la;    // particle index from the brick's first slot
+  int part;  // lane within the group
+  int T;     // lanes per particle
+};
+__device__ __forceinline__ int lane_group_T(int m, int width) {
+  int T = 16;
+  while (T > 2 && m * T > width) T >>= 1;
+  return T;
+}
+// Group of this thread in the pass starting at particle p0; false if none.
+__device__ __forceinline__ bool lane_group(int p0, int npart, LaneGroup& lg) {
+  const int width = (int)blockDim.x, half = width >> 1, t = (int)threadIdx.x;
+  const int m = npart - p0 < half ? npart - p0 : half;
+  const int T = m == half ? 2 : lane_group_T(m, width);
+  if (t >= m * T) return false;
+  lg.la = p0 + t / T;
+  lg.part = t % T;
+  lg.T = T;
+  return true;
+}
+template <typename V>
+__device__ __forceinline__ V group_sum(V v, int T) {
+  for (int off = 1; off < T; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Plain FP32 pass.  Phase 1: the pair loop of every particle of the brick
+// (its own coordinates from its tile slot) into LDS sums; a group with an
+// entry in the band walks its list again with the exact rule.  Phase 2: one
+// thread per particle stores the force or applies the fused kick-kick-drift,
+// so that none of the FP64 state of the kick is live in the pair loop.
+template <typename OT>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
-void k_lj_force32(const double* __restrict__ x, const double* __restrict__ y,
-                  const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g,
-                  TileList tl, LJConst c, F32Const k, ForceOut out) {
-  using Tile = std::conditional_t<ENERGY, TileShared, TileF4>;
-  __shared__ Tile t;
-  __shared__ double red[48];  // up to 16 waves: e, w, ke
+void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__ y,
+                        const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g,
+                        TileList tl, LJConst c, F32Const k, ForceOut out) {
+  __shared__ TileF32 t;
+  __shared__ uint16_t home[kBrickMax];
+  __shared__ float fs[3][kBrickMax];
   __shared__ double vred[16];
   if (out.fuse) kick_publish(out.track, vred);
   const int brick = brick_of_block(g);
@@ -352,175 +386,219 @@ void k_lj_force32(const double* __restrict__ x, const double* __restrict__ y,
     if (out.fuse && threadIdx.x == 0) kick_store(out.track, 0.0);
     return;
   }
-  const int total = tile_cells(g, brick, cs, t);
+  // the tile tables as the list build left them
+  const int total = tile_tables_load(g, tl.tab + (int64_t)brick * kTabInts, t);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  const int npart = s1 - s0 < kBrickMax ? s1 - s0 : kBrickMax;  // more: flagged by the build
   double ox, oy, oz;
   tile_centre(g, brick, ox, oy, oz);
-  if constexpr (ENERGY) tile_load<true>(g, x, y, z, total, t);
-  else tile_load_f4(g, x, y, z, total, ox, oy, oz, t);
-  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
-  double scale = out.scale;
-  if (out.scale_dev) scale *= *out.scale_dev;
-  double e = 0.0, w = 0.0, ke = 0.0, vmax2 = 0.0;
-  constexpr int LPP = 2;
-  const int part = (int)threadIdx.x % LPP;
-  for (int s = s0 + (int)threadIdx.x / LPP; s < s1; s += (int)blockDim.x / LPP) {
-    // the plain pass keeps only FP32 values live across the pair loop; the
-    // FP64 position is loaded again where it is needed (redo, kick)
-    float xi, yi, zi;
-    double xs = 0.0, ys = 0.0, zs = 0.0;
-    if constexpr (ENERGY) {
-      xs = x[s];
-      ys = y[s];
-      zs = z[s];
-      xi = rel32(xs, ox);
-      yi = rel32(ys, oy);
-      zi = rel32(zs, oz);
-    } else {
-      xi = rel32(x[s], ox);
-      yi = rel32(y[s], oy);
-      zi = rel32(z[s], oz);
-    }
+  tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);
+  for (int p0 = 0; p0 < npart; p0 += (int)blockDim.x >> 1) {
+    LaneGroup lg;
+    if (!lane_group(p0, npart, lg)) continue;
+    const int s = s0 + lg.la;
+    const int hu = home[lg.la];
+    const float xi = t.px[hu], yi = t.py[hu], zi = t.pz[hu];
     const int ngroups = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
+    const int64_t step = (int64_t)lg.T * tl.stride;
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    double ei = 0.0;
     bool band = false;
-    uint64_t next = part < ngroups ? col[(int64_t)part * tl.stride] : 0;
-    for (int gi = part; gi < ngroups; gi += LPP) {
+    auto pair = [&](unsigned e) {
+      // e: 4 x the partner's slot, its byte offset in the three arrays
+      const float dx = xi - *(const float*)((const char*)t.px + e);
+      const float dy = yi - *(const float*)((const char*)t.py + e);
+      const float dz = zi - *(const float*)((const char*)t.pz + e);
+      const float d2f = d2_32(dx, dy, dz);
+      const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
+      band |= lo != hi;
+      const float gf = lj_g32(d2f, lo, k);
+      ax = __builtin_fmaf(gf, dx, ax);
+      ay = __builtin_fmaf(gf, dy, ay);
+      az = __builtin_fmaf(gf, dz, az);
+    };
+    // one word (four entries) per trip; the next trip's word is loaded
+    // while this one's entries are computed
+    const uint64_t* __restrict__ p = col + (int64_t)lg.part * tl.stride;
+    uint64_t next = lg.part < ngroups ? *p : 0;
+    for (int gi = lg.part; gi < ngroups; gi += lg.T) {
       const uint64_t word = next;
-      if (gi + LPP < ngroups) next = col[(int64_t)(gi + LPP) * tl.stride];
-      if constexpr (ENERGY) {
+      p += step;
+      if (gi + lg.T < ngroups) next = *p;
 #pragma unroll
+      for (int m = 0; m < 4; ++m) pair((unsigned)(word >> (16 * m)) & 0xffffu);
+    }
+    // an entry in the band: the group walks again with the exact rule
+    if (group_sum((int)band, lg.T) != 0) {
+      const double xr = x[s], yr = y[s], zr = z[s];
+      ax = ay = az = 0.0f;
+      for (int gi = lg.part; gi < ngroups; gi += lg.T) {
+        const uint64_t word = col[(int64_t)gi * tl.stride];
         for (int m = 0; m < 4; ++m) {
-          // entry: 16 x the partner's slot; half of it in the 8-byte arrays
-          const unsigned off8 = ((unsigned)(word >> (16 * m)) & 0xffffu) >> 1;
-          const double qx = *(const double*)((const char*)t.x + off8);
-          const double qy = *(const double*)((const char*)t.y + off8);
-          const double qz = *(const double*)((const char*)t.z + off8);
-          const float dx = xi - rel32(qx, ox);
-          const float dy = yi - rel32(qy, oy);
-          const float dz = zi - rel32(qz, oz);
+          const unsigned u = (unsigned)(word >> (16 * m + kFullShift)) & 0x3fffu;
+          const float dx = xi - t.px[u], dy = yi - t.py[u], dz = zi - t.pz[u];
           const float d2f = d2_32(dx, dy, dz);
-          const double d2 = d2_image(xs, ys, zs, qx, qy, qz);
           const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
-          const bool in = lo != hi ? d2 < c.rc2 : lo;
-          // pair energy and virial in FP64
-          double s6;
-          const double gg = lj_g64(lj_inv64(d2), c, s6);
-          ei += in ? 0.5 * lj_v64(s6, c) : 0.0;
-          w += in ? 0.5 * gg * d2 : 0.0;
+          bool in = lo;
+          if (lo != hi && u != (unsigned)TileF32::kDummy) {
+            double qx, qy, qz;
+            slot_image(t, g, x, y, z, (int)u, qx, qy, qz);
+            in = d2_image(xr, yr, zr, qx, qy, qz) < c.rc2;
+          }
           const float gf = lj_g32(d2f, in, k);
           ax = __builtin_fmaf(gf, dx, ax);
           ay = __builtin_fmaf(gf, dy, ay);
           az = __builtin_fmaf(gf, dz, az);
         }
-      } else {
-        // the word's four partners are read before any is used
-        float4 q[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          q[m] = *(const float4*)((const char*)t.p + ((unsigned)(word >> (16 * m)) & 0xffffu));
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const float dx = xi - q[m].x, dy = yi - q[m].y, dz = zi - q[m].z;
-          const float d2f = d2_32(dx, dy, dz);
-          const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
-          band |= lo != hi;
-          const float gf = lj_g32(d2f, lo, k);
-          ax = __builtin_fmaf(gf, dx, ax);
-          ay = __builtin_fmaf(gf, dy, ay);
-          az = __builtin_fmaf(gf, dz, az);
-        }
       }
     }
-    if constexpr (!ENERGY) {
-      // an entry in the band: both lanes of the particle walk again with the exact rule
-      bool redo = band;
-      if (LPP == 2) redo = redo || __shfl_xor((int)band, 1, 64) != 0;
-      if (redo) {
-        const double xr = x[s], yr = y[s], zr = z[s];
-        ax = ay = az = 0.0f;
-        for (int gi = part; gi < ngroups; gi += LPP) {
-          const uint64_t word = col[(int64_t)gi * tl.stride];
-          for (int m = 0; m < 4; ++m) {
-            const unsigned u = (unsigned)(word >> (16 * m + kFullShift)) & 0xfffu;
-            const float4 q = t.p[u];
-            const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-            const float d2f = d2_32(dx, dy, dz);
-            const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
-            bool in = lo;
-            if (lo != hi && u != (unsigned)Tile::kDummy) {
-              double qx, qy, qz;
-              slot_image(t, g, x, y, z, (int)u, qx, qy, qz);
-              in = d2_image(xr, yr, zr, qx, qy, qz) < c.rc2;
-            }
-            const float gf = lj_g32(d2f, in, k);
-            ax = __builtin_fmaf(gf, dx, ax);
-            ay = __builtin_fmaf(gf, dy, ay);
-            az = __builtin_fmaf(gf, dz, az);
-          }
-        }
-      }
+    ax = group_sum(ax, lg.T);
+    ay = group_sum(ay, lg.T);
+    az = group_sum(az, lg.T);
+    if (lg.part == 0) {
+      fs[0][lg.la] = ax;
+      fs[1][lg.la] = ay;
+      fs[2][lg.la] = az;
     }
-    if (LPP == 2) {
-      ax += __shfl_xor(ax, 1, 64);
-      ay += __shfl_xor(ay, 1, 64);
-      az += __shfl_xor(az, 1, 64);
-      if (ENERGY) ei += __shfl_xor(ei, 1, 64);
-      if (part) continue;
-    }
+  }
+  __syncthreads();
+  double scale = out.scale;
+  if (out.scale_dev) scale *= *out.scale_dev;
+  double vmax2 = 0.0;
+  for (int la = threadIdx.x; la < npart; la += blockDim.x) {
+    const int s = s0 + la;
+    // the kicks use the force as stored (rounded to OT), like k_vv
+    const OT fx = (OT)((double)fs[0][la] * scale);
+    const OT fy = (OT)((double)fs[1][la] * scale);
+    const OT fz = (OT)((double)fs[2][la] * scale);
     if (out.fuse) {
-      if constexpr (!ENERGY) {
-        xs = x[s];
-        ys = y[s];
-        zs = z[s];
-      }
-      // the kicks use the force as stored (rounded to OT), like k_vv
       double m2;
-      ke += fused_kick(out, s, xs, ys, zs, out.vx[s], out.vy[s], out.vz[s],
-                       (double)(OT)((double)ax * scale), (double)(OT)((double)ay * scale),
-                       (double)(OT)((double)az * scale), m2);
+      (void)fused_kick(out, s, x[s], y[s], z[s], out.vx[s], out.vy[s], out.vz[s], (double)fx,
+                       (double)fy, (double)fz, m2);
       vmax2 = m2 > vmax2 ? m2 : vmax2;
-      if (ENERGY) e += ei;
-      continue;
-    }
-    const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
-    ((OT*)out.fx)[o] = (OT)((double)ax * scale);
-    ((OT*)out.fy)[o] = (OT)((double)ay * scale);
-    ((OT*)out.fz)[o] = (OT)((double)az * scale);
-    if (ENERGY) {
-      if (out.e_atom) out.e_atom[o] = ei;
-      e += ei;
+    } else {
+      const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
+      ((OT*)out.fx)[o] = fx;
+      ((OT*)out.fy)[o] = fy;
+      ((OT*)out.fz)[o] = fz;
     }
   }
   if (out.fuse && out.track.ring) block_track(out.track, vmax2, vred);
-  if (ENERGY) {
-    e = wave_sum(e);
-    w = wave_sum(w);
-    ke = wave_sum(ke);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-      red[wave] = e;
-      red[16 + wave] = w;
-      red[32 + wave] = ke;
+}
+
+// Energy FP32 pass: the FP64 image positions in the tile (energy and virial
+// are FP64 per pair); the FP32 coordinates of each partner are formed from
+// them with the plain tile's conversion, the pairs summed by the same lane
+// groups, and every entry classified by the exact rule.
+template <typename OT>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict__ y,
+                         const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g,
+                         TileList tl, LJConst c, F32Const k, ForceOut out) {
+  __shared__ TileShared t;
+  __shared__ double red[48];  // up to 16 waves: e, w, ke
+  __shared__ double vred[16];
+  if (out.fuse) kick_publish(out.track, vred);
+  const int brick = brick_of_block(g);
+  if (brick >= g.nbricks) {
+    if (out.fuse && threadIdx.x == 0) kick_store(out.track, 0.0);
+    return;
+  }
+  const int total = tile_cells(g, brick, cs, t);
+  double ox, oy, oz;
+  tile_centre(g, brick, ox, oy, oz);
+  tile_load<true>(g, x, y, z, total, t);
+  const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
+  const int npart = s1 - s0 < kBrickMax ? s1 - s0 : kBrickMax;
+  double scale = out.scale;
+  if (out.scale_dev) scale *= *out.scale_dev;
+  double e = 0.0, w = 0.0, ke = 0.0, vmax2 = 0.0;
+  for (int p0 = 0; p0 < npart; p0 += (int)blockDim.x >> 1) {
+    LaneGroup lg;
+    if (!lane_group(p0, npart, lg)) continue;
+    const int s = s0 + lg.la;
+    const double xs = x[s], ys = y[s], zs = z[s];
+    const float xi = rel32(xs, ox), yi = rel32(ys, oy), zi = rel32(zs, oz);
+    const int ngroups = (tl.cnt[s] + 3) >> 2;
+    const uint64_t* __restrict__ col = tl.nbr + s;
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    double ei = 0.0;
+    for (int gi = lg.part; gi < ngroups; gi += lg.T) {
+      const uint64_t word = col[(int64_t)gi * tl.stride];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        // entry: 4 x the partner's slot; twice it in the 8-byte arrays
+        const unsigned off8 = ((unsigned)(word >> (16 * m)) & 0xffffu) << 1;
+        const double qx = *(const double*)((const char*)t.x + off8);
+        const double qy = *(const double*)((const char*)t.y + off8);
+        const double qz = *(const double*)((const char*)t.z + off8);
+        const float dx = xi - rel32(qx, ox);
+        const float dy = yi - rel32(qy, oy);
+        const float dz = zi - rel32(qz, oz);
+        const float d2f = d2_32(dx, dy, dz);
+        const double d2 = d2_image(xs, ys, zs, qx, qy, qz);
+        const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
+        const bool in = lo != hi ? d2 < c.rc2 : lo;
+        // pair energy and virial in FP64
+        double s6;
+        const double gg = lj_g64(lj_inv64(d2), c, s6);
+        ei += in ? 0.5 * lj_v64(s6, c) : 0.0;
+        w += in ? 0.5 * gg * d2 : 0.0;
+        const float gf = lj_g32(d2f, in, k);
+        ax = __builtin_fmaf(gf, dx, ax);
+        ay = __builtin_fmaf(gf, dy, ay);
+        az = __builtin_fmaf(gf, dz, az);
+      }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int nw = (blockDim.x + 63) >> 6;
-      double pe = 0.0, ww = 0.0, kk = 0.0;
-      for (int q = 0; q < nw; ++q) {
-        pe += red[q];
-        ww += red[16 + q];
-        kk += red[32 + q];
-      }
-      if (out.fuse) {
-        out.partials[3 * brick] = pe;
-        out.partials[3 * brick + 1] = ww;
-        out.partials[3 * brick + 2] = kk;
-      } else {
-        out.partials[2 * brick] = pe;
-        out.partials[2 * brick + 1] = ww;
-      }
+    ax = group_sum(ax, lg.T);
+    ay = group_sum(ay, lg.T);
+    az = group_sum(az, lg.T);
+    ei = group_sum(ei, lg.T);
+    if (lg.part != 0) continue;
+    const OT fx = (OT)((double)ax * scale);
+    const OT fy = (OT)((double)ay * scale);
+    const OT fz = (OT)((double)az * scale);
+    e += ei;
+    if (out.fuse) {
+      double m2;
+      ke += fused_kick(out, s, xs, ys, zs, out.vx[s], out.vy[s], out.vz[s], (double)fx, (double)fy,
+                       (double)fz, m2);
+      vmax2 = m2 > vmax2 ? m2 : vmax2;
+      continue;
+    }
+    const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
+    ((OT*)out.fx)[o] = fx;
+    ((OT*)out.fy)[o] = fy;
+    ((OT*)out.fz)[o] = fz;
+    if (out.e_atom) out.e_atom[o] = ei;
+  }
+  if (out.fuse && out.track.ring) block_track(out.track, vmax2, vred);
+  // brick sums: wave butterflies, then the wave sums in order
+  e = wave_sum(e);
+  w = wave_sum(w);
+  ke = wave_sum(ke);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wave] = e;
+    red[16 + wave] = w;
+    red[32 + wave] = ke;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double pe = 0.0, ww = 0.0, kk = 0.0;
+    for (int q = 0; q < nw; ++q) {
+      pe += red[q];
+      ww += red[16 + q];
+      kk += red[32 + q];
+    }
+    if (out.fuse) {
+      out.partials[3 * brick] = pe;
+      out.partials[3 * brick + 1] = ww;
+      out.partials[3 * brick + 2] = kk;
+    } else {
+      out.partials[2 * brick] = pe;
+      out.partials[2 * brick + 1] = ww;
     }
   }
 }
@@ -587,10 +665,10 @@ hipError_t lj_force(const double* x, const double* y, const double* z, const int
       const dim3 grid(tile_grid(g));
       const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
       if (energy)
-        hipLaunchKernelGGL((k_lj_force32<float, true>), grid, dim3(two), 0, st, x, y, z, cell_start,
-                           g, tl, c, k, out);
+        hipLaunchKernelGGL((k_lj_force32_energy<float>), grid, dim3(two), 0, st, x, y, z,
+                           cell_start, g, tl, c, k, out);
       else
-        hipLaunchKernelGGL((k_lj_force32<float, false>), grid, dim3(two), 0, st, x, y, z,
+        hipLaunchKernelGGL((k_lj_force32_plain<float>), grid, dim3(two), 0, st, x, y, z,
                            cell_start, g, tl, c, k, out);
       break;
     }

@@ -133,6 +133,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t, HALF);
+  if (!HALF && tl.tab) tile_tables_store(g, t, tl.tab + (int64_t)brick * kTabInts);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const int nbrick = s1 - s0;
   if (threadIdx.x == 0 && (total > TS::kCap || nbrick > kBrickMax))

@@ -28,6 +28,8 @@
 
 namespace mdpl {
 
+constexpr int kHomeBit = 64;  // in a tile cell's code: the cell belongs to the brick
+
 template <typename T, int CAP>
 struct TileOf {
   static constexpr int kSlots = CAP;
@@ -56,14 +58,18 @@ struct TileXYOf {
   int code[kTileCells];
   uint8_t cell[CAP];
 };
-// FP32 force pass: x, y, z of a slot relative to the tile centre in one
-// 16-byte value; a full-list entry (16 x slot) is its byte offset
+// FP32 force pass: x, y, z of a slot relative to the tile centre in three
+// arrays (three 4-byte gathers per entry conflict less in the LDS banks than
+// one 12-byte gather at a 16-byte stride); a full-list entry (4 x slot) is
+// the byte offset in each
 template <int CAP>
-struct TileF4Of {
+struct TileF32Of {
   static constexpr int kSlots = CAP;
   static constexpr int kDummy = CAP - 1;
   static constexpr int kCap = CAP - 1;
-  float4 p[CAP];
+  float px[CAP];
+  float py[CAP];
+  float pz[CAP];
   int prefix[kTileCells + 1];
   int src[kTileCells];
   int code[kTileCells];
@@ -83,7 +89,7 @@ using TileShared32 = TileOf<float, kTileMax>;
 using TileHalf = TileOf<double, kTileMaxHalf>;
 using TileHalf32 = TileOf<float, kTileMaxHalf>;
 using TileXY = TileXYOf<kTileMax>;
-using TileF4 = TileF4Of<kTileMax>;
+using TileF32 = TileF32Of<kTileMax>;
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // run of bricks (a slab of the box) so that tile reloads hit its own L2.
@@ -133,7 +139,11 @@ __device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __rest
     const int b = cs[key];
     t.src[tc] = b;
     t.prefix[tc + 1] = tc < first ? 0 : cs[key + 1] - b;
-    t.code[tc] = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4);
+    // bit 6: a cell of the brick itself (inside the box; a partial brick's
+    // missing cells are images of other bricks' cells)
+    const bool home = lx >= 1 && lx <= g.B[0] && ly >= 1 && ly <= g.B[1] && lz >= 1 &&
+                      lz <= g.B[2] && (sx | sy | sz) == 0;
+    t.code[tc] = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4) | (home ? kHomeBit : 0);
   }
   if (threadIdx.x == 0) t.prefix[0] = 0;
   __syncthreads();
@@ -151,6 +161,30 @@ __device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __rest
       if (i <= ntc) t.prefix[i] = v + carry;
       carry += __shfl(v, 63, 64);
     }
+  }
+  __syncthreads();
+  return t.prefix[ntc];
+}
+
+// The tables tile_cells filled, to global memory (kTabInts ints: prefix,
+// then src, then code at fixed offsets), and back.  tile_tables_load ends
+// with a barrier and returns the particle count.
+template <typename TS>
+__device__ inline void tile_tables_store(const Grid& g, const TS& t, int32_t* __restrict__ tab) {
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  for (int i = threadIdx.x; i <= ntc; i += blockDim.x) tab[i] = t.prefix[i];
+  for (int i = threadIdx.x; i < ntc; i += blockDim.x) {
+    tab[kTileCells + 1 + i] = t.src[i];
+    tab[2 * kTileCells + 1 + i] = t.code[i];
+  }
+}
+template <typename TS>
+__device__ inline int tile_tables_load(const Grid& g, const int32_t* __restrict__ tab, TS& t) {
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  for (int i = threadIdx.x; i <= ntc; i += blockDim.x) t.prefix[i] = tab[i];
+  for (int i = threadIdx.x; i < ntc; i += blockDim.x) {
+    t.src[i] = tab[kTileCells + 1 + i];
+    t.code[i] = tab[2 * kTileCells + 1 + i];
   }
   __syncthreads();
   return t.prefix[ntc];
@@ -244,25 +278,52 @@ __device__ __forceinline__ void tile_centre(const Grid& g, int brick, double& ox
 // FP32 coordinate of an image position relative to the tile centre.
 __device__ __forceinline__ float rel32(double image, double o) { return (float)(image - o); }
 
-// tile_load for the FP32 tile: rel32 of the image positions.  Ends with a
-// barrier.
+// tile_load for the FP32 tile: rel32 of the image positions.  home (LDS,
+// kBrickMax entries) receives the tile slot of each of the brick's own
+// particles (by index from s0; the dummy slot for a particle the tile could
+// not hold).  Ends with a barrier.
 template <int CAP>
-__device__ inline void tile_load_f4(const Grid& g, const double* __restrict__ x,
-                                    const double* __restrict__ y, const double* __restrict__ z,
-                                    int total, double ox, double oy, double oz,
-                                    TileF4Of<CAP>& t) {
+__device__ inline void tile_load_f32(const Grid& g, const double* __restrict__ x,
+                                     const double* __restrict__ y, const double* __restrict__ z,
+                                     int total, double ox, double oy, double oz, int s0,
+                                     TileF32Of<CAP>& t, uint16_t* home) {
+  using T = TileF32Of<CAP>;
   const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
-  const int nt = total < TileF4Of<CAP>::kCap ? total : TileF4Of<CAP>::kCap;
-  tile_slot_cells(ntc, total, t);
-  if (threadIdx.x == 0)  // padding slot: no pair with it is ever inside the cutoff
-    t.p[TileF4Of<CAP>::kDummy] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
-    const int lo = t.cell[u];
-    const int src = t.src[lo] + (u - t.prefix[lo]);
-    const int code = t.code[lo];
-    t.p[u] = make_float4(rel32(image_coord(x[src], code & 3, g.box[0]), ox),
-                         rel32(image_coord(y[src], (code >> 2) & 3, g.box[1]), oy),
-                         rel32(image_coord(z[src], (code >> 4) & 3, g.box[2]), oz), 0.0f);
+  const int nt = total < T::kCap ? total : T::kCap;
+  for (int a = threadIdx.x; a < kBrickMax; a += blockDim.x) home[a] = T::kDummy;
+  tile_slot_cells(ntc, total, t);  // its barrier orders the clearing above
+  if (threadIdx.x == 0) {  // padding slot: no pair with it is ever inside the cutoff
+    t.px[T::kDummy] = 1e18f;
+    t.py[T::kDummy] = 1e18f;
+    t.pz[T::kDummy] = 1e18f;
+  }
+  // up to kPer slots per thread, all loads issued before any is used
+  constexpr int kPer = 3;
+  for (int base = 0; base < nt; base += kPer * (int)blockDim.x) {
+    double vx[kPer], vy[kPer], vz[kPer];
+    int code[kPer], src[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int u = base + j * (int)blockDim.x + (int)threadIdx.x;
+      if (u < nt) {
+        const int lo = t.cell[u];
+        src[j] = t.src[lo] + (u - t.prefix[lo]);
+        code[j] = t.code[lo];
+        vx[j] = x[src[j]];
+        vy[j] = y[src[j]];
+        vz[j] = z[src[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int u = base + j * (int)blockDim.x + (int)threadIdx.x;
+      if (u < nt) {
+        t.px[u] = rel32(image_coord(vx[j], code[j] & 3, g.box[0]), ox);
+        t.py[u] = rel32(image_coord(vy[j], (code[j] >> 2) & 3, g.box[1]), oy);
+        t.pz[u] = rel32(image_coord(vz[j], (code[j] >> 4) & 3, g.box[2]), oz);
+        if ((code[j] & kHomeBit) && src[j] - s0 < kBrickMax) home[src[j] - s0] = (uint16_t)u;
+      }
+    }
   }
   __syncthreads();
 }
