@@ -318,13 +318,14 @@ __device__ __forceinline__ double d2_image(double xs, double ys, double zs, doub
   return sq_sum(xs - qx, ys - qy, zs - qz);
 }
 
-// FP64 image position of tile slot u (the slot map gives its cell).
+// FP64 image position of tile slot u (its cell found by a search over the
+// tile's prefix).
 template <typename TS>
 __device__ __forceinline__ void slot_image(const TS& t, const Grid& g, const double* __restrict__ x,
                                            const double* __restrict__ y,
                                            const double* __restrict__ z, int u, double& qx,
                                            double& qy, double& qz) {
-  const int lo = t.cell[u];
+  const int lo = tile_cell_of(t, (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2), u);
   const int src = t.src[lo] + (u - t.prefix[lo]);
   const int code = t.code[lo];
   qx = image_coord(x[src], code & 3, g.box[0]);
@@ -334,26 +335,30 @@ __device__ __forceinline__ void slot_image(const TS& t, const Grid& g, const dou
 
 // Lane groups of the FP32 pair loops, shared by the plain and the energy
 // pass so that both sum a particle's pairs in the same order.  The brick's
-// particles are taken in passes of blockDim/2 with two lanes each; a last,
-// partial pass of m particles gives each T lanes, T the largest power of two
-// up to 16 with m T <= blockDim, so that a few leftover particles do not hold
-// the workgroup for a whole pass.  Lane p of a group takes the list words
-// p, p + T, p + 2T, ...; the group's sums are combined by butterflies.
+// particles are taken in passes of kGroupWidth/2 with two lanes each; a
+// last, partial pass of m particles gives each T lanes, T the largest power
+// of two up to 16 with m T <= kGroupWidth, so that a few leftover particles
+// do not hold the workgroup for a whole pass.  Lane p of a group takes the
+// list words p, p + T, p + 2T, ...; the group's sums are combined by
+// butterflies.  A pass has kGroupWidth lane slots, which a workgroup of
+// fewer threads runs in turns (slot t on thread t mod blockDim, the same
+// lane of a wave, since blockDim is a multiple of 64).
+constexpr int kGroupWidth = 1024;
 struct LaneGroup {
   int la;    // particle index from the brick's first slot
   int part;  // lane within the group
   int T;     // lanes per particle
 };
-__device__ __forceinline__ int lane_group_T(int m, int width) {
+__device__ __forceinline__ int lane_group_T(int m) {
   int T = 16;
-  while (T > 2 && m * T > width) T >>= 1;
+  while (T > 2 && m * T > kGroupWidth) T >>= 1;
   return T;
 }
-// Group of this thread in the pass starting at particle p0; false if none.
-__device__ __forceinline__ bool lane_group(int p0, int npart, LaneGroup& lg) {
-  const int width = (int)blockDim.x, half = width >> 1, t = (int)threadIdx.x;
+// Group of lane slot t in the pass starting at particle p0; false if none.
+__device__ __forceinline__ bool lane_group(int p0, int npart, int t, LaneGroup& lg) {
+  constexpr int half = kGroupWidth >> 1;
   const int m = npart - p0 < half ? npart - p0 : half;
-  const int T = m == half ? 2 : lane_group_T(m, width);
+  const int T = m == half ? 2 : lane_group_T(m);
   if (t >= m * T) return false;
   lg.la = p0 + t / T;
   lg.part = t % T;
@@ -365,6 +370,12 @@ __device__ __forceinline__ V group_sum(V v, int T) {
   for (int off = 1; off < T; off <<= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+// Workgroup size of the plain FP32 pass (its LDS fits three workgroups per CU).
+#ifndef MDPL_PLAIN_THREADS
+#define MDPL_PLAIN_THREADS 512
+#endif
+constexpr int kPlainThreads = MDPL_PLAIN_THREADS;
 
 // Plain FP32 pass.  Phase 1: the pair loop of every particle of the brick
 // (its own coordinates from its tile slot) into LDS sums; a group with an
@@ -393,9 +404,11 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
   double ox, oy, oz;
   tile_centre(g, brick, ox, oy, oz);
   tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);
-  for (int p0 = 0; p0 < npart; p0 += (int)blockDim.x >> 1) {
+  for (int slot = threadIdx.x; slot < npart * 2 + kGroupWidth; slot += blockDim.x) {
+    const int p0 = (slot / kGroupWidth) * (kGroupWidth >> 1);
+    if (p0 >= npart) break;
     LaneGroup lg;
-    if (!lane_group(p0, npart, lg)) continue;
+    if (!lane_group(p0, npart, slot % kGroupWidth, lg)) continue;
     const int s = s0 + lg.la;
     const int hu = home[lg.la];
     const float xi = t.px[hu], yi = t.py[hu], zi = t.pz[hu];
@@ -513,9 +526,11 @@ void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict_
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
   double e = 0.0, w = 0.0, ke = 0.0, vmax2 = 0.0;
-  for (int p0 = 0; p0 < npart; p0 += (int)blockDim.x >> 1) {
+  for (int slot = threadIdx.x; slot < npart * 2 + kGroupWidth; slot += blockDim.x) {
+    const int p0 = (slot / kGroupWidth) * (kGroupWidth >> 1);
+    if (p0 >= npart) break;
     LaneGroup lg;
-    if (!lane_group(p0, npart, lg)) continue;
+    if (!lane_group(p0, npart, slot % kGroupWidth, lg)) continue;
     const int s = s0 + lg.la;
     const double xs = x[s], ys = y[s], zs = z[s];
     const float xi = rel32(xs, ox), yi = rel32(ys, oy), zi = rel32(zs, oz);
@@ -668,7 +683,7 @@ hipError_t lj_force(const double* x, const double* y, const double* z, const int
         hipLaunchKernelGGL((k_lj_force32_energy<float>), grid, dim3(two), 0, st, x, y, z,
                            cell_start, g, tl, c, k, out);
       else
-        hipLaunchKernelGGL((k_lj_force32_plain<float>), grid, dim3(two), 0, st, x, y, z,
+        hipLaunchKernelGGL((k_lj_force32_plain<float>), grid, dim3(kPlainThreads), 0, st, x, y, z,
                            cell_start, g, tl, c, k, out);
       break;
     }

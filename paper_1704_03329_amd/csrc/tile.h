@@ -73,7 +73,6 @@ struct TileF32Of {
   int prefix[kTileCells + 1];
   int src[kTileCells];
   int code[kTileCells];
-  uint8_t cell[CAP];
 };
 // the cell table alone (kernels that map tile indices to slots only)
 struct TileCells {
@@ -278,10 +277,13 @@ __device__ __forceinline__ void tile_centre(const Grid& g, int brick, double& ox
 // FP32 coordinate of an image position relative to the tile centre.
 __device__ __forceinline__ float rel32(double image, double o) { return (float)(image - o); }
 
-// tile_load for the FP32 tile: rel32 of the image positions.  home (LDS,
-// kBrickMax entries) receives the tile slot of each of the brick's own
+// tile_load for the FP32 tile: rel32 of the image positions, eight threads
+// per tile cell (a cell's particles are contiguous in memory; no slot map,
+// which keeps the tile small enough for three workgroups per CU).  home
+// (LDS, kBrickMax entries) receives the tile slot of each of the brick's own
 // particles (by index from s0; the dummy slot for a particle the tile could
-// not hold).  Ends with a barrier.
+// not hold).  Up to four particles per thread and cell are loaded before
+// any is used.  Ends with a barrier.
 template <int CAP>
 __device__ inline void tile_load_f32(const Grid& g, const double* __restrict__ x,
                                      const double* __restrict__ y, const double* __restrict__ z,
@@ -291,37 +293,39 @@ __device__ inline void tile_load_f32(const Grid& g, const double* __restrict__ x
   const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
   const int nt = total < T::kCap ? total : T::kCap;
   for (int a = threadIdx.x; a < kBrickMax; a += blockDim.x) home[a] = T::kDummy;
-  tile_slot_cells(ntc, total, t);  // its barrier orders the clearing above
   if (threadIdx.x == 0) {  // padding slot: no pair with it is ever inside the cutoff
     t.px[T::kDummy] = 1e18f;
     t.py[T::kDummy] = 1e18f;
     t.pz[T::kDummy] = 1e18f;
   }
-  // up to kPer slots per thread, all loads issued before any is used
-  constexpr int kPer = 3;
-  for (int base = 0; base < nt; base += kPer * (int)blockDim.x) {
-    double vx[kPer], vy[kPer], vz[kPer];
-    int code[kPer], src[kPer];
+  __syncthreads();
+  constexpr int kPer = 4;
+  const int sub = (int)threadIdx.x & 7;
+  for (int tc = (int)threadIdx.x >> 3; tc < ntc; tc += (int)blockDim.x >> 3) {
+    const int b = t.prefix[tc], e = t.prefix[tc + 1] < nt ? t.prefix[tc + 1] : nt;
+    const int code = t.code[tc];
+    const int off = t.src[tc] - b;  // sorted index of slot u: off + u
+    const bool own = (code & kHomeBit) != 0;
+    for (int u0 = b + sub; u0 < e; u0 += 8 * kPer) {
+      double vx[kPer], vy[kPer], vz[kPer];
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int u = base + j * (int)blockDim.x + (int)threadIdx.x;
-      if (u < nt) {
-        const int lo = t.cell[u];
-        src[j] = t.src[lo] + (u - t.prefix[lo]);
-        code[j] = t.code[lo];
-        vx[j] = x[src[j]];
-        vy[j] = y[src[j]];
-        vz[j] = z[src[j]];
+      for (int j = 0; j < kPer; ++j) {
+        const int u = u0 + 8 * j;
+        if (u < e) {
+          vx[j] = x[off + u];
+          vy[j] = y[off + u];
+          vz[j] = z[off + u];
+        }
       }
-    }
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int u = base + j * (int)blockDim.x + (int)threadIdx.x;
-      if (u < nt) {
-        t.px[u] = rel32(image_coord(vx[j], code[j] & 3, g.box[0]), ox);
-        t.py[u] = rel32(image_coord(vy[j], (code[j] >> 2) & 3, g.box[1]), oy);
-        t.pz[u] = rel32(image_coord(vz[j], (code[j] >> 4) & 3, g.box[2]), oz);
-        if ((code[j] & kHomeBit) && src[j] - s0 < kBrickMax) home[src[j] - s0] = (uint16_t)u;
+      for (int j = 0; j < kPer; ++j) {
+        const int u = u0 + 8 * j;
+        if (u < e) {
+          t.px[u] = rel32(image_coord(vx[j], code & 3, g.box[0]), ox);
+          t.py[u] = rel32(image_coord(vy[j], (code >> 2) & 3, g.box[1]), oy);
+          t.pz[u] = rel32(image_coord(vz[j], (code >> 4) & 3, g.box[2]), oz);
+          if (own && off + u - s0 < kBrickMax) home[off + u - s0] = (uint16_t)u;
+        }
       }
     }
   }
