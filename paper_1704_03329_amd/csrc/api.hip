@@ -909,23 +909,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     HIP_TRY(skin_check(s->partials, nb, half_skin, s->max_disp, s->flags, s->st));
   }
   // the state ends wherever the ping-pong left it: copy back what is not in the caller's arrays
-  {
-    const size_t d8 = 8 * (size_t)n, fb = (size_t)s->fbytes * n;
-    auto back = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-      return dst == src ? hipSuccess
-                        : hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->st);
-    };
-    HIP_TRY(back(user.x, cur.x, d8));
-    HIP_TRY(back(user.y, cur.y, d8));
-    HIP_TRY(back(user.z, cur.z, d8));
-    HIP_TRY(back(user.vx, cur.vx, d8));
-    HIP_TRY(back(user.vy, cur.vy, d8));
-    HIP_TRY(back(user.vz, cur.vz, d8));
-    HIP_TRY(back(user.fx, cur.fx, fb));
-    HIP_TRY(back(user.fy, cur.fy, fb));
-    HIP_TRY(back(user.fz, cur.fz, fb));
-    HIP_TRY(back(user.ids, cur.ids, 4 * (size_t)n));
-  }
+  HIP_TRY(copy_state(cur, user, n, s->fbytes, s->st));
   s->last_row_valid = sampled(nsteps);
   if (s->last_row_valid)
     HIP_TRY(hipMemcpyAsync(s->last_row, row(nsteps), 4 * sizeof(double), hipMemcpyDeviceToDevice,

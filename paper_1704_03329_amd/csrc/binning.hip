@@ -379,4 +379,36 @@ hipError_t reorder_state(const StateArrays& src, const int32_t* idx, int64_t n, 
   return hipGetLastError();
 }
 
+// dst[a][s] = src[a][s] for every array a whose two pointers differ, one
+// launch for all of them (the end of a run hands the state back).
+template <typename FT>
+__global__ void k_copy_state(StateArrays src, StateArrays dst, int64_t n) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  if (src.x != dst.x) dst.x[s] = src.x[s];
+  if (src.y != dst.y) dst.y[s] = src.y[s];
+  if (src.z != dst.z) dst.z[s] = src.z[s];
+  if (src.vx != dst.vx) dst.vx[s] = src.vx[s];
+  if (src.vy != dst.vy) dst.vy[s] = src.vy[s];
+  if (src.vz != dst.vz) dst.vz[s] = src.vz[s];
+  if (src.fx != dst.fx) ((FT*)dst.fx)[s] = ((const FT*)src.fx)[s];
+  if (src.fy != dst.fy) ((FT*)dst.fy)[s] = ((const FT*)src.fy)[s];
+  if (src.fz != dst.fz) ((FT*)dst.fz)[s] = ((const FT*)src.fz)[s];
+  if (src.ids != dst.ids) dst.ids[s] = src.ids[s];
+}
+
+hipError_t copy_state(const StateArrays& src, const StateArrays& dst, int64_t n, int fbytes,
+                      hipStream_t st) {
+  if (src.x == dst.x && src.y == dst.y && src.z == dst.z && src.vx == dst.vx && src.vy == dst.vy &&
+      src.vz == dst.vz && src.fx == dst.fx && src.fy == dst.fy && src.fz == dst.fz &&
+      src.ids == dst.ids)
+    return hipSuccess;
+  const unsigned nb = (unsigned)div_up(n, 256);
+  if (fbytes == 4)
+    hipLaunchKernelGGL(k_copy_state<float>, dim3(nb), dim3(256), 0, st, src, dst, n);
+  else
+    hipLaunchKernelGGL(k_copy_state<double>, dim3(nb), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
 }  // namespace mdpl

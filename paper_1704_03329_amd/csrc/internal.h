@@ -98,6 +98,10 @@ hipError_t reorder_state(const StateArrays& src, const int32_t* idx, int64_t n, 
                          const double* box, StateArrays& dst, double* xb, double* yb, double* zb,
                          double* bound, hipStream_t st);
 
+// dst[a] = src[a] for each of the ten arrays whose pointers differ (one launch).
+hipError_t copy_state(const StateArrays& src, const StateArrays& dst, int64_t n, int fbytes,
+                      hipStream_t st);
+
 // Neighbour list (ELL) of the analysis passes: row-major nbr[i * max_nb + m]
 // of sorted-slot indices; cnt[i] is the true count (may exceed max_nb).
 // Requires a grid with B = (1,1,1).
