@@ -48,6 +48,7 @@ typedef int32_t mdpl_status;
 #define MDPL_EHIP 6       /* a HIP runtime call failed; see mdpl_last_hip_error */
 #define MDPL_ESTATE 7     /* call out of order (e.g. forces before a build) */
 #define MDPL_EWORKSPACE 8 /* workspace too small or misaligned (256 B) */
+#define MDPL_ESCRATCH 9   /* input larger than the library's static scratch (mdpl_boa_noalloc) */
 
 /* Flag bits reported by mdpl_check. */
 #define MDPL_FLAG_NL_OVERFLOW 1u
@@ -282,6 +283,22 @@ mdpl_status mdpl_analysis_workspace_bytes(int64_t n, const double* box_host, dou
 mdpl_status mdpl_boa(const double* x, const double* y, const double* z, int64_t n,
                      const double* box_host, double rc, float* q4, float* q5, float* q6,
                      int32_t* nnb, void* workspace, size_t workspace_bytes, void* stream);
+
+/* mdpl_boa without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  The workspace of mdpl_boa is taken from a static
+ * device array of MDPL_SCRATCH_BYTES per GPU, which every GPU the library
+ * runs on holds until the process ends; nothing is allocated or freed.
+ * Returns MDPL_ESCRATCH (and enqueues nothing) if the analysis needs more
+ * than MDPL_SCRATCH_BYTES, i.e. if mdpl_analysis_workspace_bytes(n, box,
+ * rc, 1) exceeds it (about 54 bytes per particle plus 4 per cell: some 10^6
+ * particles at rho = 1, rc = 1.42).  Outputs as mdpl_boa.  Every call on one
+ * GPU shares that GPU's scratch: calls that overlap in time on one GPU
+ * (other streams or threads) race and must be serialised by the caller. */
+#define MDPL_SCRATCH_BYTES (64ull << 20)
+mdpl_status mdpl_boa_noalloc(const double* x, const double* y, const double* z, int64_t n,
+                             const double* box_host, double rc, float* q4, float* q5, float* q6,
+                             int32_t* nnb, void* stream);
 
 /* Common-neighbour analysis (Sec. 4.2, Eqs. Ei and Ei_ordered; Algs. cna_I,
  * cna_II, cna_III and max_cluster_size).  1 <= max_nb <= 64 is the capacity

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -114,6 +115,7 @@ const char* mdpl_status_string(mdpl_status s) {
     case MDPL_EHIP: return "HIP runtime error";
     case MDPL_ESTATE: return "call out of order";
     case MDPL_EWORKSPACE: return "workspace too small or misaligned";
+    case MDPL_ESCRATCH: return "input too large for the library's static scratch (MDPL_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }
@@ -1027,6 +1029,35 @@ mdpl_status mdpl_analysis_workspace_bytes(int64_t n, const double* box, double r
   return MDPL_OK;
 }
 
+// Scratch of mdpl_boa_noalloc: a static device array (each GPU holds its
+// own copy), whose device address is looked up once per device with that
+// device current; host code uses only that address, never the array's name.
+static __device__ __align__(256) unsigned char scratch[MDPL_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[256];
+
+static mdpl_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    g_last_hip_error = (int32_t)e;
+    return MDPL_EHIP;
+  }
+  if (dev < 0 || dev >= 256) return MDPL_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      g_last_hip_error = (int32_t)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return MDPL_EHIP;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return MDPL_OK;
+}
+
 mdpl_status mdpl_boa(const double* x, const double* y, const double* z, int64_t n,
                      const double* box, double rc, float* q4, float* q5, float* q6, int32_t* nnb,
                      void* ws, size_t bytes, void* stream) {
@@ -1044,6 +1075,20 @@ mdpl_status mdpl_boa(const double* x, const double* y, const double* z, int64_t 
   if (v != MDPL_OK) return v;
   HIP_TRY(boa_q(sx, sy, sz, skeys, cs, perm, n, g, rc * rc, q4, q5, q6, nnb, st));
   return MDPL_OK;
+}
+
+mdpl_status mdpl_boa_noalloc(const double* x, const double* y, const double* z, int64_t n,
+                             const double* box, double rc, float* q4, float* q5, float* q6,
+                             int32_t* nnb, void* stream) {
+  size_t need = 0;
+  mdpl_status v = mdpl_analysis_workspace_bytes(n, box, rc, 1, &need);
+  if (v != MDPL_OK) return v;
+  if (need > (size_t)MDPL_SCRATCH_BYTES) return MDPL_ESCRATCH;
+  void* ws = nullptr;
+  v = scratch_address(&ws);
+  if (v != MDPL_OK) return v;
+  // the bond-order pass writes every scratch word it reads (no clearing needed)
+  return mdpl_boa(x, y, z, n, box, rc, q4, q5, q6, nnb, ws, (size_t)MDPL_SCRATCH_BYTES, stream);
 }
 
 mdpl_status mdpl_cna(const double* x, const double* y, const double* z, int64_t n,

@@ -20,6 +20,8 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "mdpl.h")
 
 MDPL_OK, MDPL_EINVAL, MDPL_EBOX, MDPL_ECAPACITY, MDPL_ESKIN = 0, 1, 2, 3, 4
 MDPL_ENONFINITE, MDPL_EHIP, MDPL_ESTATE, MDPL_EWORKSPACE = 5, 6, 7, 8
+MDPL_ESCRATCH = 9
+MDPL_SCRATCH_BYTES = 64 << 20
 FLAG_NL_OVERFLOW, FLAG_SKIN, FLAG_NONFINITE = 1, 2, 4
 SHIFTS = {"none": 0, "paper": 1, "cutoff": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
@@ -81,6 +83,7 @@ _SIGS = {
     "mdpl_kernel_time": ([_P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I32),
     "mdpl_analysis_workspace_bytes": ([_I64, ctypes.POINTER(_D), _D, _I32, ctypes.POINTER(_SZ)], _I32),
     "mdpl_boa": ([_P, _P, _P, _I64, ctypes.POINTER(_D), _D, _P, _P, _P, _P, _P, _SZ, _P], _I32),
+    "mdpl_boa_noalloc": ([_P, _P, _P, _I64, ctypes.POINTER(_D), _D, _P, _P, _P, _P, _P], _I32),
     "mdpl_cna": ([_P, _P, _P, _I64, ctypes.POINTER(_D), _D, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
 }
 
@@ -272,6 +275,13 @@ def mdpl_boa(x, y, z, box, rc, q4, q5, q6, nnb, workspace, stream=None):
     _check(lib().mdpl_boa(_ptr(x), _ptr(y), _ptr(z), n, b, float(rc), _ptr(q4), _ptr(q5), _ptr(q6),
                           _ptr(nnb), _dev(workspace, torch.uint8), workspace.numel(), _stream(stream)),
            "mdpl_boa")
+
+
+def mdpl_boa_noalloc(x, y, z, box, rc, q4, q5, q6, nnb, stream=None):
+    n = x.numel()
+    b = (_D * 3)(*[float(v) for v in box])
+    _check(lib().mdpl_boa_noalloc(_ptr(x), _ptr(y), _ptr(z), n, b, float(rc), _ptr(q4), _ptr(q5), _ptr(q6),
+                                  _ptr(nnb), _stream(stream)), "mdpl_boa_noalloc")
 
 
 def mdpl_cna(x, y, z, box, rc, max_nb, trip, nnb, label, workspace, max_count=None, stream=None):
