@@ -368,13 +368,31 @@ mdpl_status mdpl_mlp_fwd(const mdpl_mlp_weights* w, const float* G, int64_t n, f
 /* Floats of scratch mdpl_mlp_train_grad needs for a batch of `batch` rows. */
 mdpl_status mdpl_mlp_train_floats(int64_t batch, int64_t* floats_host);
 
-/* Loss L = sum_b (y_b - target[index[b]])^2 / batch (y as above without
- * e_mean/e_sd) over the rows index[0..batch) of G, and dL/dparams.
- * grad: MDPL_MLP_PARAMS + 1 floats receiving the packed gradient and, last,
- * L.  index: nullable (rows 0..batch).  scratch: mdpl_mlp_train_floats. */
+/* Loss L = sum_b (y_b - t_b)^2 / batch (y as above without e_mean/e_sd)
+ * over the rows a = index[0..batch) of G, with the standardised target
+ * t_b = (energy[a] - e_mean) / e_sd (energy: per-atom FP64 energies indexed
+ * like G), and dL/dparams.  grad: MDPL_MLP_PARAMS + 1 floats receiving the
+ * packed gradient and, last, L.  index: nullable (rows 0..batch).
+ * scratch: mdpl_mlp_train_floats. */
 mdpl_status mdpl_mlp_train_grad(const mdpl_mlp_weights* w, const float* G, const int32_t* index,
-                                int64_t batch, const float* target, float* scratch,
+                                int64_t batch, const double* energy, float* scratch,
                                 int64_t scratch_floats, float* grad, void* stream);
+
+/* Standardisation of a training set (n rows of features G, n x 24 floats,
+ * and per-atom energies e, FP64): mu[c] = mean of feature c, sd[c] = its
+ * population standard deviation + 1e-6 (24 floats each), e_stats[0] = mean
+ * energy, e_stats[1] = its population standard deviation + 1e-12 (FP64).
+ * Sums in FP64 in a fixed order (two passes); device outputs.  scratch:
+ * MDPL_MLP_STD_SCRATCH doubles. */
+#define MDPL_MLP_STD_SCRATCH (256 * 25 + 50)
+mdpl_status mdpl_mlp_standardise(const float* G, const double* e, int64_t n, float* mu,
+                                 float* sd, double* e_stats, double* scratch, void* stream);
+
+/* The bf16 copies w1, w2, w3 (layouts as in mdpl_mlp_weights) of the packed
+ * FP32 parameters, rounded to nearest even (mdpl_adam_step refreshes them
+ * after every step; this sets them for the initial parameters). */
+mdpl_status mdpl_mlp_bf16(const float* params, uint16_t* w1, uint16_t* w2, uint16_t* w3,
+                          void* stream);
 
 /* One bias-corrected Adam step (step t >= 1) on the packed FP32 parameters
  * with moments m, v; then writes the bf16 copies w1, w2, w3 (layouts as in

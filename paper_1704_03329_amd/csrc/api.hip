@@ -1181,7 +1181,7 @@ mdpl_status mdpl_mlp_train_floats(int64_t batch, int64_t* floats) {
 }
 
 mdpl_status mdpl_mlp_train_grad(const mdpl_mlp_weights* w, const float* G, const int32_t* index,
-                                int64_t batch, const float* target, float* scratch,
+                                int64_t batch, const double* target, float* scratch,
                                 int64_t scratch_floats, float* grad, void* stream) {
   if (!mlp_ok(w) || !G || batch <= 0 || !target || !scratch || !grad) return MDPL_EINVAL;
   const int waves = mlp_train_waves(batch);
@@ -1193,6 +1193,21 @@ mdpl_status mdpl_mlp_train_grad(const mdpl_mlp_weights* w, const float* G, const
   a.inv_batch = 1.0f / (float)batch;
   HIP_TRY(mlp_train_grad(a, (hipStream_t)stream));
   HIP_TRY(mlp_sum_partials(scratch, waves, grad, (hipStream_t)stream));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_mlp_standardise(const float* G, const double* e, int64_t n, float* mu,
+                                 float* sd, double* e_stats, double* scratch, void* stream) {
+  if (!G || !e || n <= 0 || !mu || !sd || !e_stats || !scratch) return MDPL_EINVAL;
+  static_assert(MDPL_MLP_STD_SCRATCH >= kStdBlocks * 25 + 50, "standardisation scratch");
+  HIP_TRY(mlp_standardise(G, e, n, mu, sd, e_stats, scratch, (hipStream_t)stream));
+  return MDPL_OK;
+}
+
+mdpl_status mdpl_mlp_bf16(const float* params, uint16_t* w1, uint16_t* w2, uint16_t* w3,
+                          void* stream) {
+  if (!params || !w1 || !w2 || !w3) return MDPL_EINVAL;
+  HIP_TRY(bf16_weights(params, w1, w2, w3, (hipStream_t)stream));
   return MDPL_OK;
 }
 

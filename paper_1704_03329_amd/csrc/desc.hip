@@ -23,10 +23,12 @@
 // make dE/du_ij = sum_eta [ w' Phi uh + w (grad Phi - (uh . grad Phi) uh) / r
 //                          + delta w w' uh ] + sum_k dE/dG_k phi_k'(r) uh,
 // Phi(x,y,z) = sum_lm P~_l^m(z) (alpha c_m + gamma s_m), u_ij = r_j - r_i,
-// and F_a = sum_{j in N(a)} (dE/du_aj - dE/du_ja): a gather, no atomics.
-// Under u -> -u the basis P~_l^m(z) (x+iy)^m changes sign for odd l and the
-// radial and diagonal terms are even, so dE/du_aj - dE/du_ja is one
-// evaluation of dE/du_aj with K_a + K_j', K_j' = K_j with odd-l moments negated.
+// and F_a = sum_{j in N(a)} (dE_a/du_aj - dE_j/du_ja).  k_desc_bwd forms each
+// term g_ij = dE_i/du_ij once, with centre i's coefficients only, and
+// scatters it: + g_ij to particle i (a register sum) and - g_ij to
+// neighbour j (an FP32 LDS atomic on the tile slot, then one global atomic
+// per touched slot).  The order in which the atomics land varies from run to
+// run, so the last bits of the forces do too.
 #include <math.h>
 
 #include "device_util.h"

@@ -339,6 +339,14 @@ hipError_t mlp_sum_partials(const float* partial, int nwaves, float* out, hipStr
 hipError_t adam_step(float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
                      float eps, int t, unsigned short* w1, unsigned short* w2, unsigned short* w3,
                      hipStream_t st);
+// BF16 copies of the weight matrices (w1, w2, w3) of packed FP32 parameters.
+hipError_t bf16_weights(const float* p, unsigned short* w1, unsigned short* w2, unsigned short* w3,
+                        hipStream_t st);
+// Feature means mu and spreads sd (24 floats each), energy mean and spread
+// (e_stats, 2 doubles) of n training rows; scratch: kStdBlocks * 25 + 50 doubles.
+constexpr int kStdBlocks = 256;
+hipError_t mlp_standardise(const float* G, const double* e, int64_t n, float* mu, float* sd,
+                           double* e_stats, double* scratch, hipStream_t st);
 hipError_t scale_velocities(double* vx, double* vy, double* vz, int64_t n, double factor,
                             hipStream_t st);
 // FP64 block partials of a float array, and of (|f - g|^2, |g|^2) per particle.

@@ -189,7 +189,9 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
       const bool ok = row < a.n;
       if (TRAIN) {
         const int64_t ir = ok ? (a.index ? (int64_t)a.index[row] : row) : 0;
-        const float diff = ok ? ypart[r] - a.target[ir] : 0.0f;
+        // the target: the atom's energy standardised with the network's e_mean, e_sd
+        const float t = ok ? (float)((a.target[ir] - (double)a.e_mean) / (double)a.e_sd) : 0.0f;
+        const float diff = ok ? ypart[r] - t : 0.0f;
         dy[r] = 2.0f * diff * a.inv_batch;
         if (col == 0) loss += diff * diff * a.inv_batch;
       } else {
@@ -436,6 +438,87 @@ hipError_t adam_step(float* p, const float* g, float* m, float* v, float lr, flo
   const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
   hipLaunchKernelGGL(k_adam, dim3((kNParam + 255) / 256), dim3(256), 0, st, p, g, m, v, lr, b1, b2,
                      eps, c1, c2, w1, w2, w3);
+  return hipGetLastError();
+}
+
+// BF16 copies of the weight matrices from the packed FP32 parameters
+// (round to nearest even, as after every Adam step).
+__global__ void k_bf16_weights(const float* __restrict__ p, unsigned short* __restrict__ w1,
+                               unsigned short* __restrict__ w2, unsigned short* __restrict__ w3) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kNParam) return;
+  const float pk = p[k];
+  if (k < kOffB1) w1[k] = f2bf(pk);
+  else if (k >= kOffW2 && k < kOffB2) w2[k - kOffW2] = f2bf(pk);
+  else if (k >= kOffW3 && k < kOffB3) w3[k - kOffW3] = f2bf(pk);
+}
+
+hipError_t bf16_weights(const float* p, unsigned short* w1, unsigned short* w2, unsigned short* w3,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_bf16_weights, dim3((kNParam + 255) / 256), dim3(256), 0, st, p, w1, w2, w3);
+  return hipGetLastError();
+}
+
+// Standardisation statistics of the training set, FP64 in a fixed order:
+// means, then the mean squared deviations from them (two passes, as the
+// population standard deviation is defined).  Column c < 24 is feature c of
+// G (n x 24 floats), column 24 the energy.  Pass 1 (ref null): per-block
+// sums; pass 2 (ref = the means): per-block sums of squared deviations.
+constexpr int kStdCols = kNIn + 1;
+__global__ __launch_bounds__(256) void k_std_partials(const float* __restrict__ G,
+                                                      const double* __restrict__ e, int64_t n,
+                                                      const double* __restrict__ ref,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
+  for (int c = 0; c < kStdCols; ++c) {
+    const double m = ref ? ref[c] : 0.0;
+    double acc = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+      const double v = c < kNIn ? (double)G[r * kNIn + c] : e[r];
+      acc += ref ? (v - m) * (v - m) : v;
+    }
+    const double t = block_sum256(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kStdCols + c] = t;
+  }
+}
+
+// Sums the partials of every column in block order; out[c] = sum / n.  With
+// fin: the feature spreads sqrt(.) + 1e-6 to sd (float), the means to mu,
+// the energy's mean and spread sqrt(.) + 1e-12 to e_stats.
+__global__ __launch_bounds__(64) void k_std_reduce(const double* __restrict__ part, int nb,
+                                                   int64_t n, double* __restrict__ out, bool fin,
+                                                   const double* __restrict__ mean, float* mu,
+                                                   float* sd, double* e_stats) {
+  const int c = threadIdx.x;
+  if (c >= kStdCols) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * kStdCols + c];
+  const double v = s / (double)n;
+  out[c] = v;
+  if (!fin) return;
+  if (c < kNIn) {
+    mu[c] = (float)mean[c];
+    sd[c] = (float)(sqrt(v) + 1e-6);
+  } else {
+    e_stats[0] = mean[c];
+    e_stats[1] = sqrt(v) + 1e-12;
+  }
+}
+
+hipError_t mlp_standardise(const float* G, const double* e, int64_t n, float* mu, float* sd,
+                           double* e_stats, double* scratch, hipStream_t st) {
+  const int nb = kStdBlocks;
+  double* part = scratch;
+  double* mean = scratch + (int64_t)nb * kStdCols;
+  double* var = mean + kStdCols;
+  hipLaunchKernelGGL(k_std_partials, dim3(nb), dim3(256), 0, st, G, e, n, nullptr, part);
+  hipLaunchKernelGGL(k_std_reduce, dim3(1), dim3(64), 0, st, part, nb, n, mean, false, nullptr,
+                     nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(k_std_partials, dim3(nb), dim3(256), 0, st, G, e, n, mean, part);
+  hipLaunchKernelGGL(k_std_reduce, dim3(1), dim3(64), 0, st, part, nb, n, var, true, mean, mu, sd,
+                     e_stats);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ struct MlpArgs {
   int64_t n;                 // rows
   float* energy;             // EVAL: E per row (nullable)
   float* dEdG;               // EVAL: [row][24] (nullable)
-  const float* target;       // TRAIN: standardised targets per atom (indexed like G)
+  const double* target;      // TRAIN: per-atom energies (indexed like G), standardised in the kernel
   float* partial;            // TRAIN: per-wave [kNParam + 1] (gradient, loss)
   float inv_batch;           // TRAIN: 1 / B
 };

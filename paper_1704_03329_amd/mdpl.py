@@ -316,6 +316,9 @@ _SIGS_MLP = {
                             ctypes.c_int32),
     "mdpl_adam_step": ([ctypes.c_void_p] * 4 + [ctypes.c_float] * 4 + [ctypes.c_int32] + [ctypes.c_void_p] * 4,
                        ctypes.c_int32),
+    "mdpl_mlp_standardise": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 5,
+                             ctypes.c_int32),
+    "mdpl_mlp_bf16": ([ctypes.c_void_p] * 5, ctypes.c_int32),
     "mdpl_scale_velocities": ([ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_double, ctypes.c_void_p],
                               ctypes.c_int32),
     "mdpl_mlp_run_floats": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
@@ -347,9 +350,28 @@ def mdpl_mlp_train_floats(batch: int) -> int:
     return int(out.value)
 
 
-def mdpl_mlp_train_grad(w, G, index, batch, target, scratch, grad):
-    _check(lib().mdpl_mlp_train_grad(ctypes.byref(w), _ptr(G), _ptr(index), int(batch), _ptr(target), _ptr(scratch),
+def mdpl_mlp_train_grad(w, G, index, batch, energy, scratch, grad):
+    """energy: per-atom FP64 energies (the library standardises them)."""
+    if energy.dtype != torch.float64:
+        raise TypeError("energy must be float64")
+    _check(lib().mdpl_mlp_train_grad(ctypes.byref(w), _ptr(G), _ptr(index), int(batch), _ptr(energy), _ptr(scratch),
                                         scratch.numel(), _ptr(grad), _stream()), "mdpl_mlp_train_grad")
+
+
+MDPL_MLP_STD_SCRATCH = 256 * 25 + 50
+
+
+def mdpl_mlp_standardise(G, e, mu, sd, e_stats, scratch):
+    if e.dtype != torch.float64 or e_stats.dtype != torch.float64 or scratch.dtype != torch.float64:
+        raise TypeError("e, e_stats and scratch must be float64")
+    if scratch.numel() < MDPL_MLP_STD_SCRATCH:
+        raise ValueError("scratch needs MDPL_MLP_STD_SCRATCH doubles")
+    _check(lib().mdpl_mlp_standardise(_ptr(G), _ptr(e), int(G.shape[0]), _ptr(mu), _ptr(sd), _ptr(e_stats),
+                                      _ptr(scratch), _stream()), "mdpl_mlp_standardise")
+
+
+def mdpl_mlp_bf16(params, w1, w2, w3):
+    _check(lib().mdpl_mlp_bf16(_ptr(params), _ptr(w1), _ptr(w2), _ptr(w3), _stream()), "mdpl_mlp_bf16")
 
 
 def mdpl_adam_step(params, grad, m, v, lr, b1, b2, eps, step, w1, w2, w3):

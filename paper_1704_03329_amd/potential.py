@@ -27,8 +27,11 @@ from .mdpl import (  # noqa: E402  (re-exported names of the C entry points)
     mdpl_desc_bwd,
     mdpl_desc_fwd,
     mdpl_force_error,
+    MDPL_MLP_STD_SCRATCH,
+    mdpl_mlp_bf16,
     mdpl_mlp_fwd,
     mdpl_mlp_run_floats,
+    mdpl_mlp_standardise,
     mdpl_run_mlp,
     mdpl_mlp_train_floats,
     mdpl_mlp_train_grad,
@@ -50,11 +53,6 @@ def unpack(v) -> dict:
     return {k: v[off:off + int(np.prod(shape))].reshape(shape) for k, (off, shape) in OFF.items()}
 
 
-def bf16_bits(a: torch.Tensor) -> torch.Tensor:
-    """float32 device tensor -> bfloat16 bit patterns (int16), nearest-even."""
-    return a.to(torch.bfloat16).view(torch.int16).contiguous()
-
-
 class MLPPotential:
     """Parameters on the device: FP32 master vector, Adam moments, BF16 copies
     of the weight matrices, biases (views of the master vector), feature and
@@ -65,9 +63,10 @@ class MLPPotential:
         self.params = torch.from_numpy(pack(mdinputs.mlp_init(seed))).to(self.device)
         self.m = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
         self.v = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
-        self.w1 = bf16_bits(self.params[0:2048])
-        self.w2 = bf16_bits(self.params[2112:6208])
-        self.w3 = bf16_bits(self.params[6272:6336])
+        self.w1 = torch.empty(2048, dtype=torch.int16, device=self.device)
+        self.w2 = torch.empty(4096, dtype=torch.int16, device=self.device)
+        self.w3 = torch.empty(64, dtype=torch.int16, device=self.device)
+        mdpl_mlp_bf16(self.params, self.w1, self.w2, self.w3)
         self.mu = torch.zeros(24, dtype=torch.float32, device=self.device)
         self.sd = torch.ones(24, dtype=torch.float32, device=self.device)
         self.e_mean = 0.0
@@ -93,25 +92,24 @@ class MLPPotential:
         return d
 
     def set_standardisation(self, G: torch.Tensor, e: torch.Tensor):
-        g = G.double().cpu().numpy()
-        ee = e.double().cpu().numpy()
-        self.mu = torch.from_numpy(g.mean(0).astype(np.float32)).to(self.device)
-        self.sd = torch.from_numpy((g.std(0) + 1e-6).astype(np.float32)).to(self.device)
-        self.e_mean = float(ee.mean())
-        self.e_sd = float(ee.std() + 1e-12)
+        """Feature and energy statistics of the training set (mdpl_mlp_standardise)."""
+        stats = torch.empty(2, dtype=torch.float64, device=self.device)
+        scratch = torch.empty(MDPL_MLP_STD_SCRATCH, dtype=torch.float64, device=self.device)
+        mdpl_mlp_standardise(G.contiguous(), e.contiguous(), self.mu, self.sd, stats, scratch)
+        self.e_mean, self.e_sd = (float(v) for v in stats.cpu())
 
     def train(self, G: torch.Tensor, e: torch.Tensor, steps: int, batch: int = 4096, lr: float = 1e-3,
               seed: int = 99, log_every: int = 0, lr_final: float | None = None):
         """Adam on L = mean (y - (e - e_mean)/e_sd)^2 over random batches."""
         n = G.shape[0]
-        target = ((e.double() - self.e_mean) / self.e_sd).float().contiguous()
+        energy = e.to(torch.float64).contiguous()
         idx = torch.from_numpy(mdinputs.batch_indices(n, batch, steps, seed)).to(self.device)
         scratch = torch.empty(mdpl_mlp_train_floats(batch), dtype=torch.float32, device=self.device)
         grad = torch.empty(NPARAM + 1, dtype=torch.float32, device=self.device)
         losses = []
         w = self.weights()
         for k in range(steps):
-            mdpl_mlp_train_grad(w, G, idx[k], batch, target, scratch, grad)
+            mdpl_mlp_train_grad(w, G, idx[k], batch, energy, scratch, grad)
             self.step += 1
             rate = lr if lr_final is None else lr * (lr_final / lr) ** (k / max(steps - 1, 1))
             mdpl_adam_step(self.params, grad, self.m, self.v, rate, 0.9, 0.999, 1e-8, self.step, self.w1, self.w2,
@@ -138,7 +136,7 @@ class MLPPotential:
     def forces(self, sim: LJSim, x, y, z, buf: dict | None = None):
         """(per-atom energies, fx, fy, fz) for positions already built in sim:
         descriptors and their moments, network energies and dE/dG, then the
-        gather-form descriptor backward."""
+        descriptor backward (a scatter of the pair terms)."""
         n = sim.n
         b = buf if buf is not None else self.buffers(n)
         mdpl_desc_fwd(sim, x, y, z, b["G"], b["mom"])

@@ -117,19 +117,21 @@ def test_train_gradient_and_adam_match_oracle(config):
     Gd = P.descriptors(sim, torch.from_numpy(pos).cuda())
     e = torch.from_numpy(np.sin(np.arange(n) * 0.37) - 4.0).cuda()
     m = _model(Gd, e, seed=4)
-    target = ((e.double() - m.e_mean) / m.e_sd).float().contiguous()
+    # the kernel standardises the energies with the network's (FP32) e_mean, e_sd
+    em, es = float(np.float32(m.e_mean)), float(np.float32(m.e_sd))
+    target = (e.double() - em) / es
     batch = 500
     idx = torch.from_numpy(mdinputs.batch_indices(n, batch, 1, 12)[0]).cuda()
     scratch = torch.empty(P.mdpl_mlp_train_floats(batch), dtype=torch.float32, device="cuda")
     grad = torch.empty(P.NPARAM + 1, dtype=torch.float32, device="cuda")
-    P.mdpl_mlp_train_grad(m.weights(), Gd, idx, batch, target, scratch, grad)
+    P.mdpl_mlp_train_grad(m.weights(), Gd, idx, batch, e.double().contiguous(), scratch, grad)
     g = grad.cpu().numpy()
     # oracle on the same rows, same bf16-rounded weights
     p = m.host_params()
     rows = idx.cpu().numpy()
     gstd = OM.standardise(Gd.double().cpu().numpy()[rows], m.mu.double().cpu().numpy(),
                           m.sd.double().cpu().numpy())
-    L, ref = OM.loss_and_grads(p, gstd, target.double().cpu().numpy()[rows])
+    L, ref = OM.loss_and_grads(p, gstd, target.cpu().numpy()[rows])
     assert g[P.NPARAM] == pytest.approx(L, rel=2e-2)
     refv = P.pack(ref).astype(np.float64)
     assert _rel(g[: P.NPARAM], refv) <= 3e-2
@@ -144,6 +146,39 @@ def test_train_gradient_and_adam_match_oracle(config):
     want = OM.adam_step({"a": before}, {"a": g[: P.NPARAM].astype(np.float64)}, {}, lr=1e-3)["a"]
     want[:2048].reshape(64, 32)[:, 24:] = 0.0
     np.testing.assert_allclose(after, want, rtol=1e-5, atol=1e-7)
+
+
+def test_standardisation_and_bf16_cast_in_the_library():
+    """mdpl_mlp_standardise: FP64 means and population spreads of the
+    features and energies (the definition, written out in numpy here);
+    mdpl_mlp_bf16: the bf16 copies round to nearest even, bit for bit as
+    torch's conversion."""
+    from paper_1704_03329_amd import potential as P
+
+    r = mdinputs.rng(21)
+    n = 70_001
+    G = torch.from_numpy((r.normal(size=(n, 24)) * np.linspace(0.1, 30.0, 24) + 5.0).astype(np.float32)).cuda()
+    e = torch.from_numpy(r.normal(-4.2, 0.8, size=n)).cuda()
+    mu = torch.empty(24, dtype=torch.float32, device="cuda")
+    sd = torch.empty_like(mu)
+    st = torch.empty(2, dtype=torch.float64, device="cuda")
+    scratch = torch.empty(P.MDPL_MLP_STD_SCRATCH, dtype=torch.float64, device="cuda")
+    P.mdpl_mlp_standardise(G, e, mu, sd, st, scratch)
+    g = G.double().cpu().numpy()
+    ee = e.cpu().numpy()
+    np.testing.assert_allclose(mu.cpu().numpy(), g.mean(0), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(sd.cpu().numpy(), np.sqrt(((g - g.mean(0)) ** 2).mean(0)) + 1e-6, rtol=1e-6)
+    assert st[0].item() == pytest.approx(ee.mean(), rel=1e-12)
+    assert st[1].item() == pytest.approx(np.sqrt(((ee - ee.mean()) ** 2).mean()) + 1e-12, rel=1e-12)
+    params = torch.from_numpy(r.normal(0.0, 0.3, size=P.NPARAM).astype(np.float32)).cuda()
+    w1 = torch.empty(2048, dtype=torch.int16, device="cuda")
+    w2 = torch.empty(4096, dtype=torch.int16, device="cuda")
+    w3 = torch.empty(64, dtype=torch.int16, device="cuda")
+    P.mdpl_mlp_bf16(params, w1, w2, w3)
+    bf = lambda a: a.to(torch.bfloat16).view(torch.int16)  # noqa: E731
+    assert torch.equal(w1, bf(params[0:2048]))
+    assert torch.equal(w2, bf(params[2112:6208]))
+    assert torch.equal(w3, bf(params[6272:6336]))
 
 
 @pytest.fixture(scope="module")
