@@ -106,26 +106,76 @@ def measured_flops(avg_s, entries):
             "source": "rocprofv3 SQ_INSTS_VALU_FLOPS_* counters (profiles/lj_force_f32_n1m_flops.txt)"}
 
 
-def cpu_baseline(pos, box, rows: int):
-    """The FP64 all-pairs oracle on a bounded sample of the same workload:
-    forces for `rows` atoms against all N (one step's force work for them)."""
-    import numpy as np
-
+def cpu_baseline(pos, vel, box):
+    """The FP64 oracle on the same workload: one velocity-Verlet step of the
+    whole N = 10^6 system (oracle.lj.velocity_verlet with the k-d tree route
+    of lj_forces_tree: candidate pairs on all host threads, then the
+    definition's minimum-image test and pair terms in numpy).  The run also
+    computes F(r0), so a step is taken as half of the elapsed time."""
     from oracle import lj as olj
 
-    sample = np.sort(np.random.Generator(np.random.PCG64(7)).choice(pos.shape[0], rows, replace=False))
+    n = pos.shape[0]
+    threads = os.cpu_count()
     t0 = time.perf_counter()
-    olj.lj_forces(pos, box, 2.5, rows=sample)
+    olj.velocity_verlet(pos, vel, box, 1, 0.001, 2.5, shift="cutoff",
+                        force_fn=lambda r: olj.lj_forces_tree(r, box, 2.5, shift="cutoff"))
     dt = time.perf_counter() - t0
     return {
-        "value": rows / dt,
+        "value": n / (dt / 2.0),
         "unit": "atom-steps/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"FP64 all-pairs minimum-image LJ forces of {rows} random atoms against all "
-                  f"{pos.shape[0]} (numpy, single thread; host has {os.cpu_count()} cores); "
-                  f"{dt:.1f} s; velocity-Verlet updates not included",
+        "sample": f"one FP64 velocity-Verlet step of all {n} atoms (the oracle's k-d tree route: scipy cKDTree "
+                  f"candidates with workers=-1 on {threads} host threads, then numpy on one thread for the "
+                  f"exact minimum-image test, forces and updates); F(r0) + 1 step took {dt:.1f} s, "
+                  "a step = half of it; no neighbour-list reuse",
     }
+
+
+def oracle_analysis_rate():
+    """The analysis oracles (all-pairs neighbour sets; scipy spherical
+    harmonics for Q4/Q6; CNA with Python sets) on a bounded sample: every
+    atom of a 5,000-atom polycrystal of the same recipe (their cost grows as
+    N^2, so this rate is an upper bound of theirs at N = 4e6)."""
+    import mdinputs
+    from oracle import boa as ob
+    from oracle import cna as oc
+
+    pc = mdinputs.polycrystal(5_000, 4, seed=3)
+    pos, box, rc = pc["pos"], pc["box"], 1.2684 * pc["d"]
+    n = pos.shape[0]
+    t0 = time.perf_counter()
+    ob.bond_order(pos, box, rc, ls=(4, 6))
+    t_boa = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oc.cna(pos, box, rc)
+    t_cna = time.perf_counter() - t0
+    return {"boa_atoms_per_s": n / t_boa, "cna_atoms_per_s": n / t_cna, "cores": 1, "kind": "oracle",
+            "sample": f"all {n} atoms of a 4-grain polycrystal (rho 1, jitter 0.05 d, seed 3); numpy/scipy on "
+                      f"one thread; BOA {t_boa:.1f} s, CNA {t_cna:.1f} s"}
+
+
+def oracle_mlp_rate(pos, box, model):
+    """The learned potential's FP64 oracle (direct descriptor triple sums,
+    the network, the chain rule for forces) on 200 sampled centres of the
+    evaluation configuration, with the same bf16-rounded weights."""
+    import numpy as np
+
+    from oracle import descriptor as OD
+    from oracle import mlp as OM
+
+    rows = np.sort(np.random.Generator(np.random.PCG64(45)).choice(pos.shape[0], 200, replace=False))
+    p = model.host_params()
+    mu = model.mu.double().cpu().numpy()
+    sd = model.sd.double().cpu().numpy()
+    t0 = time.perf_counter()
+    G, table, grads = OD.descriptors(pos, box, rows=rows, with_grad=True)
+    _, dEdG = OM.energy_and_feature_grad(p, G, mu, sd, model.e_mean, model.e_sd)
+    OD.forces_from_feature_grad(pos.shape[0], rows, table, grads, dEdG)
+    dt = time.perf_counter() - t0
+    return {"atoms_per_s": rows.shape[0] / dt, "cores": 1, "kind": "oracle",
+            "sample": f"{rows.shape[0]} centres of the N={pos.shape[0]} evaluation configuration: descriptors, "
+                      f"energies, dE/dG and their force terms in FP64 numpy on one thread, {dt:.1f} s"}
 
 
 def event_time(fn, reps: int) -> float:
@@ -215,6 +265,7 @@ def mlp_report(args):
     t_lj = event_time(lj_force, reps)
     t_mlp = event_time(lambda: model.forces(ref, x, y, z, buf), reps)
     t_build = event_time(lambda: ref.build(x, y, z), 10)
+    oracle = oracle_mlp_rate(pos.cpu().numpy(), box, model) if not args.no_cpu_baseline else None
     log(f"MLP: LJ force {t_lj * 1e6:.1f} us, MLP energy+forces {t_mlp * 1e6:.1f} us, build {t_build * 1e6:.1f} us")
     return {
         "workload": f"MLP 24-64-64-1 (16 radial + 8 angular features within 2.5, BF16 weights, FP32 "
@@ -222,6 +273,8 @@ def mlp_report(args):
                     "trained on 180 + 20 validation snapshots of N=4000 at T* 0.7/1.0/1.5",
         "n_atoms": n,
         "mlp_us_per_eval": t_mlp * 1e6,
+        "mlp_atoms_per_s": n / t_mlp,
+        "oracle": oracle,
         "lj_fp32_us_per_eval": t_lj * 1e6,
         "nlist_build_us": t_build * 1e6,
         "time_ratio_mlp_over_lj": t_mlp / t_lj,
@@ -237,7 +290,7 @@ def mlp_report(args):
     }
 
 
-def analysis_report():
+def analysis_report(with_oracle: bool = True):
     """Bond order (Q4, Q6) and CNA on the structure-analysis workload: 50
     FCC/HCP/BCC grains, N ~ 4e6, rho 1, jitter 0.05 d, seed 3, cutoff 1.2684 d."""
     import numpy as np
@@ -270,7 +323,9 @@ def analysis_report():
     max_bonds = int(most.item())
     log(f"analysis: BOA {t_boa * 1e3:.2f} ms, CNA {t_cna * 1e3:.2f} ms (capacity {cap}, "
         f"largest bond count {max_bonds})")
+    oracle = oracle_analysis_rate() if with_oracle else None
     return {
+        "oracle": oracle,
         "workload": f"50 FCC/HCP/BCC grains, N={n}, rho 1.0, jitter 0.05 d, seed 3, cutoff {rc:.4f} "
                     "(neighbour list, bond order and CNA each included)",
         "n_atoms": n,
@@ -327,7 +382,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n-side", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=1024)
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
     ap.add_argument("--mlp-steps", type=int, default=6000)
@@ -385,8 +439,8 @@ def main():
     n = d["pos"].shape[0]
     box = d["box"]
     log(f"N={n} box={box[0]:.4f} building context")
-    def timed_run(pairs, warmup, steps):
-        sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision="fp32", shift="cutoff",
+    def timed_run(pairs, warmup, steps, precision="fp32"):
+        sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision=precision, shift="cutoff",
                     max_nb=128, pairs=pairs, rebuild=args.rebuild)
         state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
         torch.cuda.synchronize()
@@ -476,7 +530,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": {"full": "k_lj_force<float,float,false> (with the fused kick-kick-drift)",
+            "kernel": {"full": "k_lj_force32_plain<float> (with the fused kick-kick-drift)",
                        "half": "k_lj_force_half<float,float,false,false> (with the clearing of the forces)",
                        "cells": "k_lj_force_cells<float,float,false>"}[args.pairs],
             "achieved": achieved,
@@ -528,15 +582,28 @@ def main():
                 "nlist_entries_per_atom": h["entries"] / n,
                 "note": note,
             }
+    if args.pairs == "full" and not args.no_pairs_compare:
+        # the paper's precision (FP64 pair forces), same workload, as context
+        hs = min(args.steps, 200)
+        h = timed_run("full", min(args.warmup, 20), hs, precision="fp64")
+        out["fp64_forces"] = {
+            "value": n * hs / h["elapsed"],
+            "unit": "atom-steps/s",
+            "steps": hs,
+            "ms_per_step": h["elapsed"] / hs * 1e3,
+            "force_us": h["f_ms"] / max(h["f_n"], 1) * 1e3,
+            "force_energy_virial_us": h["fe_ms"] / max(h["fe_n"], 1) * 1e3,
+            "note": "FP64 pair forces and sums (the paper's precision); everything else as the headline run",
+        }
     if not args.no_mlp:
         out["mlp_vs_lj"] = mlp_report(args)
     if not args.no_analysis:
-        out["analysis"] = analysis_report()
+        out["analysis"] = analysis_report(not args.no_cpu_baseline)
     if not args.no_onthefly:
         out["on_the_fly"] = onthefly_report(args)
     if not args.no_cpu_baseline:
-        log(f"oracle CPU baseline on {args.cpu_rows} atoms")
-        out["cpu_baseline"] = cpu_baseline(d["pos"], box, args.cpu_rows)
+        log("oracle CPU baseline: one FP64 step of the whole system")
+        out["cpu_baseline"] = cpu_baseline(d["pos"], d["vel"], box)
     print(json.dumps(out), flush=True)
 
 

@@ -160,6 +160,68 @@ def lj_forces(pos, box, rc: float, eps: float = 1.0, sigma: float = 1.0, shift: 
     return {"F": F, "e": e, "pe": float(np.sum(e)), "w": float(np.sum(w_i)), "nb": nb}
 
 
+# --------------------------------------------------------------------------
+# The same results for large N: scipy's k-d tree proposes candidate pairs,
+# the definition above decides (the tree's own distance test is never
+# trusted; its radius is padded so that it can only over-propose).
+# --------------------------------------------------------------------------
+
+def candidate_pairs(pos, box, radius: float, workers: int = -1):
+    """Directed pairs (i, j), i != j, a superset of those closer than radius
+    (cKDTree over the folded positions, periodic, all host threads)."""
+    from scipy.spatial import cKDTree
+
+    pos = np.asarray(pos, dtype=np.float64)
+    folded = wrap(pos, box)
+    tree = cKDTree(folded, boxsize=np.asarray(box, dtype=np.float64))
+    pad = float(radius) * (1.0 + 1e-9) + 1e-9
+    lists = tree.query_ball_point(folded, pad, workers=workers, return_sorted=False)
+    cnt = np.fromiter((len(a) for a in lists), dtype=np.int64, count=len(lists))
+    j = np.concatenate(lists).astype(np.int64) if cnt.sum() else np.zeros(0, dtype=np.int64)
+    i = np.repeat(np.arange(len(lists), dtype=np.int64), cnt)
+    keep = i != j
+    return i[keep], j[keep]
+
+
+def _pair_separations(pos, box, i, j):
+    """dr = r_i - r_j (min image, the definition's operation order) and d2 for pairs."""
+    pos = np.asarray(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    dx = min_image(pos[i, 0] - pos[j, 0], box[0])
+    dy = min_image(pos[i, 1] - pos[j, 1], box[1])
+    dz = min_image(pos[i, 2] - pos[j, 2], box[2])
+    d2 = (dx * dx + dy * dy) + dz * dz
+    return dx, dy, dz, d2
+
+
+def neighbour_pairs_tree(pos, box, r2: float, workers: int = -1) -> np.ndarray:
+    """neighbour_pairs for all rows, through candidate_pairs (sorted, int64 (P, 2))."""
+    i, j = candidate_pairs(pos, box, math.sqrt(r2), workers)
+    d2 = _pair_separations(pos, box, i, j)[3]
+    m = d2 < r2
+    p = np.stack([i[m], j[m]], axis=1)
+    return p[np.lexsort((p[:, 1], p[:, 0]))]
+
+
+def lj_forces_tree(pos, box, rc: float, eps: float = 1.0, sigma: float = 1.0, shift: str = "none",
+                   workers: int = -1):
+    """lj_forces for every atom, through candidate_pairs: the same pairs and
+    pair terms, summed per atom in another order (so equal to rounding)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    rc2 = float(rc) * float(rc)
+    i, j = candidate_pairs(pos, box, float(rc), workers)
+    dx, dy, dz, d2 = _pair_separations(pos, box, i, j)
+    m = d2 < rc2
+    i, dx, dy, dz, d2 = i[m], dx[m], dy[m], dz[m], d2[m]
+    g = lj_force_factor_r2(d2, eps, sigma)
+    v = lj_potential_r2(d2, eps, sigma, shift, rc)
+    F = np.stack([np.bincount(i, g * dx, n), np.bincount(i, g * dy, n), np.bincount(i, g * dz, n)], axis=1)
+    e = 0.5 * np.bincount(i, v, n)
+    w = 0.5 * float(np.sum(g * d2))
+    return {"F": F, "e": e, "pe": float(np.sum(e)), "w": w, "nb": np.bincount(i, minlength=n)}
+
+
 def kinetic_energy(vel, mass: float = 1.0) -> float:
     """K = sum_i 1/2 m |v_i|^2 (the Particle Loop example of Sec. 2)."""
     vel = np.asarray(vel, dtype=np.float64)

@@ -50,6 +50,32 @@ def test_descriptors_match_oracle(config):
         assert _rel(G[:, f], ref[:, f]) <= 1e-5, f
 
 
+def test_descriptors_match_oracle_brick_tiles():
+    """The 1e-5 descriptor bar where the tiles are 3^3-cell bricks that do
+    not wrap onto themselves: every atom of a jittered 4000-atom FCC box (the
+    training configuration, 6 cells per axis), and sampled rows of the
+    262,144-atom evaluation configuration (a jittered 64^3 lattice)."""
+    from paper_1704_03329_amd.potential import descriptors
+
+    d = mdinputs.fcc_lj(10, temperature=1.0, seed=40)
+    pos = mdinputs.perturb(d["pos"], 0.1, 7)
+    box = d["box"]
+    sim = _sim(pos.shape[0], box)
+    G = descriptors(sim, torch.from_numpy(pos).cuda()).cpu().numpy()
+    ref = OD.descriptors(pos, box)
+    for f in range(OD.NFEAT):
+        assert _rel(G[:, f], ref[:, f]) <= 1e-5, f
+    pos, box = mdinputs.sc_lattice(64)
+    pos = mdinputs.perturb(pos, 0.08, 43)
+    n = pos.shape[0]
+    sim = _sim(n, box)
+    G = descriptors(sim, torch.from_numpy(pos).cuda()).cpu().numpy()
+    rows = np.sort(mdinputs.rng(44).choice(n, 600, replace=False))
+    ref = OD.descriptors(pos, box, rows=rows)
+    for f in range(OD.NFEAT):
+        assert _rel(G[rows, f], ref[:, f]) <= 1e-5, f
+
+
 def _model(G, e, seed=3):
     from paper_1704_03329_amd.potential import MLPPotential
 

@@ -287,3 +287,22 @@ def test_rebuild_schedule_reuse_cap_and_carry():
     # a faster stretch shortens the periods
     gaps = np.diff([0] + whole)
     assert gaps[0] == 18 and gaps[-1] < 18
+
+
+@pytest.mark.parametrize("n_side,jit", [(12, 0.07), (16, 0.15)])
+def test_tree_route_equals_all_pairs(n_side, jit):
+    """The large-N route (k-d tree candidates, then the definition's test)
+    gives the all-pairs neighbour set bit for bit and the same forces,
+    energies and virial to rounding (the sums run in another order)."""
+    pos, box = mdinputs.sc_lattice(n_side)
+    pos = mdinputs.perturb(pos, jit, 90 + n_side)
+    r2 = lj.ext_radius_sq(2.5, 0.3)
+    assert np.array_equal(lj.neighbour_pairs_tree(pos, box, r2), lj.neighbour_pairs(pos, box, r2))
+    a = lj.lj_forces(pos, box, 2.5, shift="cutoff")
+    b = lj.lj_forces_tree(pos, box, 2.5, shift="cutoff")
+    assert np.array_equal(a["nb"], b["nb"])
+    scale = np.max(np.abs(a["F"]))
+    assert np.max(np.abs(a["F"] - b["F"])) <= 1e-12 * scale
+    assert b["pe"] == pytest.approx(a["pe"], rel=1e-12)
+    assert b["w"] == pytest.approx(a["w"], rel=1e-12)
+    assert np.max(np.abs(a["e"] - b["e"])) <= 1e-12 * np.max(np.abs(a["e"]))

@@ -191,3 +191,31 @@ def test_linear_fit_recovers_linear_model():
     a2, c = M.linear_fit(G, e)
     np.testing.assert_allclose(a2, a, rtol=1e-10)
     assert c == pytest.approx(0.3)
+
+
+def test_adam_bias_correction_over_several_steps():
+    """With a constant gradient the bias-corrected moments are exactly g and
+    g^2 at every step t (1 - b^t cancels the geometric sum), so each step
+    moves by lr g / (|g| + eps): after t steps p0 - t lr g / (|g| + eps).
+    A correction with the wrong power of beta (or none) misses this from
+    t = 2 on.  With a gradient that flips sign at t = 2, the second step has
+    the closed form m2 = (1-b1)(b1 g1 + g2) / (1-b1^2) and
+    v2 = (1-b2)(b2 g1^2 + g2^2) / (1-b2^2)."""
+    p0 = np.array([1.0, -2.0, 0.25])
+    g = np.array([0.5, -0.1, 3.0])
+    st = {}
+    p = {"a": p0.copy()}
+    for t in range(1, 7):
+        p = M.adam_step(p, {"a": g}, st, lr=0.01, b1=0.9, b2=0.999, eps=1e-8)
+        want = p0 - t * 0.01 * g / (np.abs(g) + 1e-8)
+        np.testing.assert_allclose(p["a"], want, rtol=0, atol=1e-12)
+    g1, g2 = np.array([0.5, 0.2]), np.array([-0.3, 0.2])
+    st = {}
+    p = M.adam_step({"a": np.zeros(2)}, {"a": g1}, st, lr=0.01)
+    p = M.adam_step(p, {"a": g2}, st, lr=0.01)
+    b1, b2 = 0.9, 0.999
+    m2 = (b1 * g1 + g2) / (1 + b1)          # (1-b1)(b1 g1 + g2) / (1 - b1^2)
+    v2 = (b2 * g1 * g1 + g2 * g2) / (1 + b2)
+    step1 = 0.01 * g1 / (np.abs(g1) + 1e-8)
+    want = -step1 - 0.01 * m2 / (np.sqrt(v2) + 1e-8)
+    np.testing.assert_allclose(p["a"], want, rtol=1e-12, atol=1e-15)
