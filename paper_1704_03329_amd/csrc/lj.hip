@@ -517,10 +517,11 @@ void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict_
     if (out.fuse && threadIdx.x == 0) kick_store(out.track, 0.0);
     return;
   }
-  const int total = tile_cells(g, brick, cs, t);
+  // the tile tables as the list build left them
+  const int total = tile_tables_load(g, tl.tab + (int64_t)brick * kTabInts, t);
   double ox, oy, oz;
   tile_centre(g, brick, ox, oy, oz);
-  tile_load<true>(g, x, y, z, total, t);
+  tile_load_f64_cells(g, x, y, z, total, t);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const int npart = s1 - s0 < kBrickMax ? s1 - s0 : kBrickMax;
   double scale = out.scale;

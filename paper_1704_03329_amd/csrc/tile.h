@@ -332,6 +332,53 @@ __device__ inline void tile_load_f32(const Grid& g, const double* __restrict__ x
   __syncthreads();
 }
 
+// FP64 image positions into a TileOf<double> cell by cell, eight threads per
+// cell and up to four particles each loaded before use (no slot map is
+// filled).  Ends with a barrier.
+template <int CAP>
+__device__ inline void tile_load_f64_cells(const Grid& g, const double* __restrict__ x,
+                                           const double* __restrict__ y,
+                                           const double* __restrict__ z, int total,
+                                           TileOf<double, CAP>& t) {
+  using T = TileOf<double, CAP>;
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int nt = total < T::kCap ? total : T::kCap;
+  if (threadIdx.x == 0) {  // padding slot: no pair with it is ever inside the cutoff
+    t.x[T::kDummy] = 1e20;
+    t.y[T::kDummy] = 1e20;
+    t.z[T::kDummy] = 1e20;
+  }
+  constexpr int kPer = 4;
+  const int sub = (int)threadIdx.x & 7;
+  for (int tc = (int)threadIdx.x >> 3; tc < ntc; tc += (int)blockDim.x >> 3) {
+    const int b = t.prefix[tc], e = t.prefix[tc + 1] < nt ? t.prefix[tc + 1] : nt;
+    const int code = t.code[tc];
+    const int off = t.src[tc] - b;  // sorted index of slot u: off + u
+    for (int u0 = b + sub; u0 < e; u0 += 8 * kPer) {
+      double vx[kPer], vy[kPer], vz[kPer];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int u = u0 + 8 * j;
+        if (u < e) {
+          vx[j] = x[off + u];
+          vy[j] = y[off + u];
+          vz[j] = z[off + u];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int u = u0 + 8 * j;
+        if (u < e) {
+          t.x[u] = image_coord(vx[j], code & 3, g.box[0]);
+          t.y[u] = image_coord(vy[j], (code >> 2) & 3, g.box[1]);
+          t.z[u] = image_coord(vz[j], (code >> 4) & 3, g.box[2]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Tile cell of tile particle u < total (binary search over the prefix;
 // a tile has at least 27 cells, so the first halving always happens), for
 // tables without the slot map.
