@@ -24,6 +24,7 @@ mdpl_status make_grid(const double box[3], double r, const int brick[3], Grid* g
     if (q > 4096.0) q = 4096.0;
     g->nc[k] = (int)q;
     g->inv_side[k] = q / box[k];
+    g->side[k] = box[k] / q;
     g->box[k] = box[k];
     int b = brick[k] < 1 ? 1 : brick[k];
     if (b > g->nc[k]) b = g->nc[k];

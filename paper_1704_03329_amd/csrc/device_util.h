@@ -55,6 +55,51 @@ __device__ __forceinline__ double sq_sum(double dx, double dy, double dz) {
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// Cross-lane moves on DPP (data-parallel primitives: a lane reads another
+// lane's register within the same instruction, no LDS round trip as with
+// __shfl).  CTRL: 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = quad_perm
+// [2,3,0,1] (lane ^ 2), 0x110 + n = row_shr:n, 0x142 / 0x143 =
+// row_bcast:15 / row_bcast:31 (ROWS selects the rows written; a lane with
+// no source keeps 0).
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(dpp_i32<CTRL, ROWS>(__float_as_int(v)));
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  return __hiloint2double(dpp_i32<CTRL, ROWS>(__double2hiint(v)),
+                          dpp_i32<CTRL, ROWS>(__double2loint(v)));
+}
+
+// Largest value over the 64 lanes of a wave (all active), for values >= 0:
+// a running maximum within each row of 16 lanes, then across rows; lane 63
+// ends with the wave's maximum, which is returned to every lane.
+__device__ __forceinline__ int wave_max_nonneg(int v) {
+  int o;
+  o = dpp_i32<0x111>(v); v = o > v ? o : v;
+  o = dpp_i32<0x112>(v); v = o > v ? o : v;
+  o = dpp_i32<0x114>(v); v = o > v ? o : v;
+  o = dpp_i32<0x118>(v); v = o > v ? o : v;
+  o = dpp_i32<0x142, 0xa>(v); v = o > v ? o : v;
+  o = dpp_i32<0x143, 0xc>(v); v = o > v ? o : v;
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  double o;
+  o = dpp_move<0x111>(v); v = o > v ? o : v;
+  o = dpp_move<0x112>(v); v = o > v ? o : v;
+  o = dpp_move<0x114>(v); v = o > v ? o : v;
+  o = dpp_move<0x118>(v); v = o > v ? o : v;
+  o = dpp_move<0x142, 0xa>(v); v = o > v ? o : v;
+  o = dpp_move<0x143, 0xc>(v); v = o > v ? o : v;
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

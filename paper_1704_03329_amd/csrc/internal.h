@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/mdpl.h"
+#include "device_util.h"
 
 namespace mdpl {
 
@@ -34,6 +35,7 @@ struct Grid {
   int nbricks;
   int nkeys;  // nbricks * V
   double inv_side[3];
+  double side[3];  // box / nc, the cell edge
   double box[3];
   // tile kernels: brick of each of their norder workgroups (device, nbricks
   // for padding); null: the order of brick_of_block
@@ -203,11 +205,7 @@ __device__ inline void kick_publish(const KickTrack& kt, double* sh) {
   const double* p = kt.part[kt.cur ^ 1];
   double m = 0.0;
   for (int i = threadIdx.x; i < kt.pub_n; i += blockDim.x) m = p[i] > m ? p[i] : m;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(m, off, 64);
-    m = o > m ? o : m;
-  }
+  m = wave_max_nonneg(m);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {

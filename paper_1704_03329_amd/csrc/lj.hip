@@ -88,11 +88,7 @@ __device__ __forceinline__ double lj_v64(double s6, const LJConst& c) {
 // Largest |v|^2 of the workgroup (v2 per thread, 0 where none) to the rule's
 // tracking; one barrier.
 __device__ __forceinline__ void block_track(const KickTrack& kt, double v2, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(v2, off, 64);
-    v2 = o > v2 ? o : v2;
-  }
+  v2 = wave_max_nonneg(v2);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v2;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -299,11 +295,14 @@ struct F32Const {
 
 // FP32 force factor f/dr of a pair: in selects the pair (the reciprocal of
 // FLT_MAX drives the factor of an excluded pair to zero).
-__device__ __forceinline__ float lj_g32(float d2f, bool in, const F32Const& k) {
+__device__ __forceinline__ float lj_g32(float d2f, bool in, float fa, float nfb) {
 #pragma clang fp contract(off)
   const float inv = __builtin_amdgcn_rcpf(in ? d2f : 3.0e38f);
   const float x2 = inv * inv;
-  return (x2 * x2) * __builtin_fmaf(k.fa, x2 * inv, -k.fb);
+  return (x2 * x2) * __builtin_fmaf(fa, x2 * inv, nfb);
+}
+__device__ __forceinline__ float lj_g32(float d2f, bool in, const F32Const& k) {
+  return lj_g32(d2f, in, k.fa, -k.fb);
 }
 
 __device__ __forceinline__ float d2_32(float dx, float dy, float dz) {
@@ -354,11 +353,16 @@ __device__ __forceinline__ int lane_group_T(int m) {
   while (T > 2 && m * T > kGroupWidth) T >>= 1;
   return T;
 }
+// Lanes per particle of the pass starting at particle p0 (m of its particles).
+__device__ __forceinline__ int lane_pass_T(int p0, int npart, int& m) {
+  constexpr int half = kGroupWidth >> 1;
+  m = npart - p0 < half ? npart - p0 : half;
+  return m == half ? 2 : lane_group_T(m);
+}
 // Group of lane slot t in the pass starting at particle p0; false if none.
 __device__ __forceinline__ bool lane_group(int p0, int npart, int t, LaneGroup& lg) {
-  constexpr int half = kGroupWidth >> 1;
-  const int m = npart - p0 < half ? npart - p0 : half;
-  const int T = m == half ? 2 : lane_group_T(m);
+  int m;
+  const int T = lane_pass_T(p0, npart, m);
   if (t >= m * T) return false;
   lg.la = p0 + t / T;
   lg.part = t % T;
@@ -367,7 +371,10 @@ __device__ __forceinline__ bool lane_group(int p0, int npart, int t, LaneGroup& 
 }
 template <typename V>
 __device__ __forceinline__ V group_sum(V v, int T) {
-  for (int off = 1; off < T; off <<= 1) v += __shfl_xor(v, off, 64);
+  // butterflies: lane ^ 1 and lane ^ 2 on DPP, wider ones through LDS
+  if (T > 1) v += dpp_move<0xB1>(v);
+  if (T > 2) v += dpp_move<0x4E>(v);
+  for (int off = 4; off < T; off <<= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
@@ -378,8 +385,10 @@ __device__ __forceinline__ V group_sum(V v, int T) {
 constexpr int kPlainThreads = MDPL_PLAIN_THREADS;
 
 // Plain FP32 pass.  Phase 1: the pair loop of every particle of the brick
-// (its own coordinates from its tile slot) into LDS sums; a group with an
-// entry in the band walks its list again with the exact rule.  Phase 2: one
+// (its own coordinates from its tile slot) into LDS sums; the lanes of a
+// wave take the same number of trips, so the band test of an entry costs
+// one comparison and the flags of the wave are one scalar mask; a group with
+// an entry in the band walks its list again with the exact rule.  Phase 2: one
 // thread per particle stores the force or applies the fused kick-kick-drift,
 // so that none of the FP64 state of the kick is live in the pair loop.
 template <typename OT>
@@ -404,19 +413,37 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
   double ox, oy, oz;
   tile_centre(g, brick, ox, oy, oz);
   tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);
-  for (int slot = threadIdx.x; slot < npart * 2 + kGroupWidth; slot += blockDim.x) {
-    const int p0 = (slot / kGroupWidth) * (kGroupWidth >> 1);
+  // The wave's pass and its lanes per particle are the same for all its lanes
+  // (blockDim and kGroupWidth are multiples of 64), so they live in scalar
+  // registers; every lane of the wave takes the same number of trips (the
+  // wave's longest list part, lanes past their own part read the dummy
+  // word), so that the band flags of a trip are one wave mask.
+  const int lane = (int)threadIdx.x & 63;
+  const int wbase = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
+  constexpr uint64_t kDummyWord = 0x0001000100010001ull * (uint64_t)(4 * TileF32::kDummy);
+  for (int base = wbase;; base += blockDim.x) {
+    const int p0 = (base / kGroupWidth) * (kGroupWidth >> 1);
     if (p0 >= npart) break;
-    LaneGroup lg;
-    if (!lane_group(p0, npart, slot % kGroupWidth, lg)) continue;
-    const int s = s0 + lg.la;
-    const int hu = home[lg.la];
+    int m;
+    const int T = lane_pass_T(p0, npart, m);
+    const int sh = __builtin_ctz(T);
+    const int tt = base % kGroupWidth + lane;
+    const bool has = tt < m * T;
+    const int la = has ? p0 + (tt >> sh) : 0;
+    const int part = tt & (T - 1);
+    const int s = s0 + la;
+    const int hu = home[la];
     const float xi = t.px[hu], yi = t.py[hu], zi = t.pz[hu];
-    const int ngroups = (tl.cnt[s] + 3) >> 2;
+    const int ngroups = has ? (tl.cnt[s] + 3) >> 2 : 0;
+    const int trips = ngroups > part ? (ngroups - part + T - 1) >> sh : 0;
+    const int wtrips = wave_max_nonneg(trips);
     const uint64_t* __restrict__ col = tl.nbr + s;
-    const int64_t step = (int64_t)lg.T * tl.stride;
+    const int64_t step = (int64_t)T * tl.stride;
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    bool band = false;
+    uint64_t bandm = 0;  // lanes with an entry in the band
+    // -fb in a vector register for the whole loop (an FMA takes one scalar
+    // operand, fa); the zero product keeps the compiler from folding it back
+    const float nfb = __builtin_fmaf(0.0f, xi, -k.fb);
     auto pair = [&](unsigned e) {
       // e: 4 x the partner's slot, its byte offset in the three arrays
       const float dx = xi - *(const float*)((const char*)t.px + e);
@@ -424,31 +451,34 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
       const float dz = zi - *(const float*)((const char*)t.pz + e);
       const float d2f = d2_32(dx, dy, dz);
       const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
-      band |= lo != hi;
-      const float gf = lj_g32(d2f, lo, k);
+      // the band (r2lo <= d2f < r2hi) as wave masks of the two comparisons
+      bandm |= __builtin_amdgcn_ballot_w64(hi) & ~__builtin_amdgcn_ballot_w64(lo);
+      const float gf = lj_g32(d2f, lo, k.fa, nfb);
       ax = __builtin_fmaf(gf, dx, ax);
       ay = __builtin_fmaf(gf, dy, ay);
       az = __builtin_fmaf(gf, dz, az);
     };
     // one word (four entries) per trip; the next trip's word is loaded
     // while this one's entries are computed
-    const uint64_t* __restrict__ p = col + (int64_t)lg.part * tl.stride;
-    uint64_t next = lg.part < ngroups ? *p : 0;
-    for (int gi = lg.part; gi < ngroups; gi += lg.T) {
-      const uint64_t word = next;
+    const uint64_t* __restrict__ p = col + (int64_t)part * tl.stride;
+    uint64_t next = 0;
+    if (trips > 0) next = *p;
+    for (int q = 0; q < wtrips; ++q) {
+      // a lane past its own part reads the dummy slot (no force, no band)
+      const uint64_t word = q < trips ? next : kDummyWord;
       p += step;
-      if (gi + lg.T < ngroups) next = *p;
+      if (q + 1 < trips) next = *p;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) pair((unsigned)(word >> (16 * m)) & 0xffffu);
+      for (int j = 0; j < 4; ++j) pair((unsigned)(word >> (16 * j)) & 0xffffu);
     }
     // an entry in the band: the group walks again with the exact rule
-    if (group_sum((int)band, lg.T) != 0) {
+    if ((bandm >> (lane & ~(T - 1))) & ((1ull << T) - 1)) {
       const double xr = x[s], yr = y[s], zr = z[s];
       ax = ay = az = 0.0f;
-      for (int gi = lg.part; gi < ngroups; gi += lg.T) {
+      for (int gi = part; gi < ngroups; gi += T) {
         const uint64_t word = col[(int64_t)gi * tl.stride];
-        for (int m = 0; m < 4; ++m) {
-          const unsigned u = (unsigned)(word >> (16 * m + kFullShift)) & 0x3fffu;
+        for (int j = 0; j < 4; ++j) {
+          const unsigned u = (unsigned)(word >> (16 * j + kFullShift)) & 0x3fffu;
           const float dx = xi - t.px[u], dy = yi - t.py[u], dz = zi - t.pz[u];
           const float d2f = d2_32(dx, dy, dz);
           const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
@@ -465,13 +495,13 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
         }
       }
     }
-    ax = group_sum(ax, lg.T);
-    ay = group_sum(ay, lg.T);
-    az = group_sum(az, lg.T);
-    if (lg.part == 0) {
-      fs[0][lg.la] = ax;
-      fs[1][lg.la] = ay;
-      fs[2][lg.la] = az;
+    ax = group_sum(ax, T);
+    ay = group_sum(ay, T);
+    az = group_sum(az, T);
+    if (has && part == 0) {
+      fs[0][la] = ax;
+      fs[1][la] = ay;
+      fs[2][la] = az;
     }
   }
   __syncthreads();
@@ -527,6 +557,7 @@ void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict_
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
   double e = 0.0, w = 0.0, ke = 0.0, vmax2 = 0.0;
+  const double w24 = 24.0 * c.eps;
   for (int slot = threadIdx.x; slot < npart * 2 + kGroupWidth; slot += blockDim.x) {
     const int p0 = (slot / kGroupWidth) * (kGroupWidth >> 1);
     if (p0 >= npart) break;
@@ -555,11 +586,12 @@ void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict_
         const double d2 = d2_image(xs, ys, zs, qx, qy, qz);
         const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
         const bool in = lo != hi ? d2 < c.rc2 : lo;
-        // pair energy and virial in FP64
-        double s6;
-        const double gg = lj_g64(lj_inv64(d2), c, s6);
+        // pair energy and virial in FP64; half of the pair's r f(r), which
+        // is 48 eps s6 (s6 - 1/2) with s6 = (sigma^2 / r^2)^3
+        const double s2 = c.sigma2 * lj_inv64(d2);
+        const double s6 = s2 * s2 * s2;
         ei += in ? 0.5 * lj_v64(s6, c) : 0.0;
-        w += in ? 0.5 * gg * d2 : 0.0;
+        w += in ? w24 * (s6 * (s6 - 0.5)) : 0.0;
         const float gf = lj_g32(d2f, in, k);
         ax = __builtin_fmaf(gf, dx, ax);
         ay = __builtin_fmaf(gf, dy, ay);

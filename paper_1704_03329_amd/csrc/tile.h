@@ -269,9 +269,9 @@ __device__ __forceinline__ void tile_centre(const Grid& g, int brick, double& ox
                                             double& oz) {
   int bx, by, bz;
   brick_coords(g, brick, bx, by, bz);
-  ox = ((double)(bx * g.B[0]) + 0.5 * (double)g.B[0]) * (g.box[0] / (double)g.nc[0]);
-  oy = ((double)(by * g.B[1]) + 0.5 * (double)g.B[1]) * (g.box[1] / (double)g.nc[1]);
-  oz = ((double)(bz * g.B[2]) + 0.5 * (double)g.B[2]) * (g.box[2] / (double)g.nc[2]);
+  ox = ((double)(bx * g.B[0]) + 0.5 * (double)g.B[0]) * g.side[0];
+  oy = ((double)(by * g.B[1]) + 0.5 * (double)g.B[1]) * g.side[1];
+  oz = ((double)(bz * g.B[2]) + 0.5 * (double)g.B[2]) * g.side[2];
 }
 
 // FP32 coordinate of an image position relative to the tile centre.
