@@ -92,8 +92,9 @@ def measured_flops(avg_s, entries):
         ent = float(kv["entries_per_launch"])
     except (KeyError, ValueError):
         return None
-    # the summary's launches start from the lattice (more entries than the
-    # timed run); scale the counted work to this run's entry count
+    # the summary's launches may hold another entry count than this run's
+    # (the summary is taken on the melted fluid); scale the counted work to
+    # this run's entry count
     k = entries / ent if ent > 0 else 1.0
     t32, t64 = f32 * k / avg_s / 1e12, f64 * k / avg_s / 1e12
     # vector issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
