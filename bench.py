@@ -526,8 +526,15 @@ def main():
                                 "cells": "none (each pass scans the 27-cell stencil)"}[args.pairs],
             "n_atoms": n,
             "nlist_entries_per_atom": entries / n,
-            "precision": "FP32 pair force factor, forces stored as FP32; FP64 positions, velocities, "
-                         "separations, cutoff test, per-particle force sums, energy, virial",
+            "precision": {
+                "full": "FP32 separations from tile-centred FP32 coordinates, FP32 pair force and per-particle "
+                        "sums, forces stored as FP32; the cutoff decided by the exact FP64 test within a band "
+                        "around rc^2 (the definition's pair set); FP64 positions, velocities, and FP64 "
+                        "separations, pair energies and virial on sampled steps",
+                "half": "FP32 pair force factor, forces stored as FP32; FP64 positions, velocities, "
+                        "separations, cutoff test, per-particle force sums, energy, virial",
+                "cells": "FP32 pair force factor, forces stored as FP32; FP64 positions, velocities, "
+                         "separations, cutoff test, per-particle force sums, energy, virial"}[args.pairs],
         },
         "roofline": {
             "bound": "hbm",
