@@ -5,7 +5,9 @@ and a list rebuild every 10 steps): 100^3 simple-cubic lattice at density
 0.8442, Gaussian velocities at T* = 1 (seed 2), eps = sigma = m = 1,
 rc = 2.5 (energy shifted to zero at rc, so the reported drift measures the
 integration), skin 0.3, dt = 0.001, FP32 pair forces with FP64 positions,
-separations, energies and virial; PE and virial every 10 steps.
+energies and virial; PE and virial every 10 steps.  The lattice melts in
+--premelt untimed steps (default 1000) of the same run, ahead of the warmup,
+so that a short timed run measures the fluid, as a long one does.
 
 A step is one full velocity-Verlet step of the whole path: the force pass
 (with energy/virial on every 10th step) followed in the same kernel by the
@@ -382,6 +384,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n-side", type=int, default=100)
+    ap.add_argument("--premelt", type=int, default=1000,
+                    help="untimed steps that melt the lattice before the warmup (0: start from the lattice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
@@ -440,15 +444,19 @@ def main():
     n = d["pos"].shape[0]
     box = d["box"]
     log(f"N={n} box={box[0]:.4f} building context")
+    melted = {}  # the headline run's configuration after its timed steps (the CPU baseline's input)
     def timed_run(pairs, warmup, steps, precision="fp32"):
         sim = LJSim(n, box, rc=2.5, skin=0.3, dt=0.001, reuse_every=10, precision=precision, shift="cutoff",
                     max_nb=128, pairs=pairs, rebuild=args.rebuild)
         state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
         torch.cuda.synchronize()
-        log(f"pairs={pairs}: warmup {warmup} steps")
-        # the warmup samples its last step, so that the timed run, which goes
-        # on from its state (list, forces, rebuild schedule), starts from its row
-        sim.run(state, warmup, max(warmup, 1))
+        pre = warmup + args.premelt
+        log(f"pairs={pairs}: melting the lattice and warmup, {args.premelt} + {warmup} steps")
+        # the lattice melts in the first premelt steps of the same run, which
+        # then goes on with the warmup; its last step is sampled, so that the
+        # timed run, which continues from its state (list, forces, rebuild
+        # schedule), starts from its row
+        sim.run(state, pre, max(pre, 1))
         torch.cuda.synchronize()
         st, flags, _ = sim.check(raise_on_error=False)
         if st != 0:
@@ -461,7 +469,7 @@ def main():
         log(f"timing {steps} steps")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        thermo = sim.run(state, steps, 10, cont=warmup > 0)
+        thermo = sim.run(state, steps, 10, cont=pre > 0)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         rb = [a - b for a, b in zip(sim.rebuild_stats(), rb0)]
@@ -472,6 +480,9 @@ def main():
         fe_ms, fe_n = C.mdpl_kernel_time(sim.handle, 1)
         C.mdpl_set_timing(sim.handle, False)
         entries = C.mdpl_nlist_entries(sim.handle) if pairs != "cells" else 0
+        if not melted:
+            melted["pos"] = torch.stack([state["x"], state["y"], state["z"]], 1).cpu().numpy()
+            melted["vel"] = torch.stack([state["vx"], state["vy"], state["vz"]], 1).cpu().numpy()
         log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
             f"force+energy {fe_ms / max(fe_n, 1) * 1e3:.1f} us x {fe_n}; entries/atom {entries / n:.2f}; "
             f"rebuilds {rb[0]} (early {rb[1]}, host waits {rb[2]})")
@@ -518,7 +529,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"LJ fluid N={n} ({n_side}^3 sc lattice, rho 0.8442, T*=1, seed 2), rc 2.5, "
+            "workload": f"LJ fluid N={n} ({n_side}^3 sc lattice, rho 0.8442, T*=1, seed 2, melted by "
+                        f"{args.premelt} untimed steps), rc 2.5, "
                         "skin 0.3, rebuild every 10 steps, dt 0.001, FP32 pair forces, FP64 "
                         "positions/energy/virial, PE+virial every 10 steps",
             "neighbour_lists": {"full": "full (every ordered pair)",
@@ -611,7 +623,7 @@ def main():
         out["on_the_fly"] = onthefly_report(args)
     if not args.no_cpu_baseline:
         log("oracle CPU baseline: one FP64 step of the whole system")
-        out["cpu_baseline"] = cpu_baseline(d["pos"], d["vel"], box)
+        out["cpu_baseline"] = cpu_baseline(melted["pos"], melted["vel"], box)
     print(json.dumps(out), flush=True)
 
 
