@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s LJ N=1M + HBM GB/s; MLP vs LJ time at stated force RMSE"
 HBM_PEAK_GBS = 8000.0
+# the force-kernel launches timed with HIP events: one in TIME_EVERY of each kernel
+TIME_EVERY = 8
 # every source the force kernel is compiled from (counter summaries name their hash)
 FORCE_SRC = [os.path.join(ROOT, "paper_1704_03329_amd", "csrc", f)
              for f in ("lj.hip", "tile.h", "device_util.h", "internal.h")] + \
@@ -461,8 +463,12 @@ def main():
         st, flags, _ = sim.check(raise_on_error=False)
         if st != 0:
             raise SystemExit(f"warmup flagged status {st} flags {flags}")
-        # events for every launch of the timed run are created here, not in it
-        C.mdpl_set_timing(sim.handle, not args.no_kernel_timing, reserve=steps + 8)
+        # events for the timed launches are created here, not in the run; an
+        # event pair makes the stream wait for the kernel before it (about 7
+        # us of step time per launch at this size), so one launch in
+        # TIME_EVERY of each force kernel is timed
+        C.mdpl_set_timing(sim.handle, not args.no_kernel_timing, reserve=steps // TIME_EVERY + 8,
+                          every=TIME_EVERY)
         C.mdpl_kernel_time(sim.handle, 0)  # reset
         C.mdpl_kernel_time(sim.handle, 1)
         rb0 = sim.rebuild_stats()
@@ -560,7 +566,8 @@ def main():
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": avg_s * 1e6,
-            "launches": f_n,
+            "timed_launches": f_n,
+            "timed_every": TIME_EVERY,
         },
         "flops": flops,
         # context only, another machine and precision: the paper's framework on

@@ -249,14 +249,18 @@ mdpl_status mdpl_check(mdpl_sim* sim, uint32_t* flags_host, int32_t* max_count_h
 /* Clear the device flags and the largest-count record (enqueued). */
 mdpl_status mdpl_clear_flags(mdpl_sim* sim);
 
-/* Kernel timing on the context's stream with HIP events.  When on, mdpl_run
- * brackets every launch of the force kernels with an event pair; on > 1
- * creates events for that many launches up front, so that none is created
- * while a timed run is enqueued (events are reused afterwards).
+/* Kernel timing on the context's stream with HIP events.  When on, the runs
+ * bracket launches 0, every, 2 every, ... of each force kernel (every >= 1;
+ * 1: all of them) with an event pair: each pair makes the stream wait for
+ * the kernel before it and costs a few microseconds of step time, so a
+ * stride above 1 times a sample of the launches at a fraction of that cost.
+ * on > 1 creates events for that many launches up front, so that none is
+ * created while a timed run is enqueued (events are reused afterwards).
  * mdpl_kernel_time synchronises and returns the summed milliseconds and the
- * number of launches for `which` = 0 (plain force pass) or 1 (force pass
- * with energy and virial), then resets the record. */
-mdpl_status mdpl_set_timing(mdpl_sim* sim, int32_t on);
+ * number of timed launches for `which` = 0 (plain force pass) or 1 (force
+ * pass with energy and virial), then resets the record.  MDPL_EINVAL for
+ * on < 0 or every < 1. */
+mdpl_status mdpl_set_timing(mdpl_sim* sim, int32_t on, int32_t every);
 mdpl_status mdpl_kernel_time(mdpl_sim* sim, int32_t which, double* ms_host, int64_t* launches_host);
 
 /* Rebuilds of the runs of this context so far (host counters, no

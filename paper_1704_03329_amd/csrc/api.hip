@@ -32,6 +32,8 @@ int32_t g_last_hip_error = 0;
 struct Timing {
   std::vector<hipEvent_t> ev[2];  // start/stop pairs, flattened
   std::vector<hipEvent_t> pool;   // created, not recorded (reused across timed runs)
+  int64_t launches[2] = {0, 0};   // launches of each kind since the last read
+  int every = 1;                  // time launches 0, every, 2 every, ... of each kind
 };
 
 // run kinds whose state a continued run may take over
@@ -260,6 +262,12 @@ double shift_value(const mdpl_lj_params* p) {
 }
 
 // An event from the pool (created only when the pool is empty).
+// Whether this launch of the given kind is bracketed with events.
+bool timed_launch(mdpl_sim* s, int slot) {
+  if (!s->timing || slot < 0) return false;
+  return (s->tm.launches[slot]++ % s->tm.every) == 0;
+}
+
 hipError_t take_event(mdpl_sim* s, hipEvent_t* e) {
   if (!s->tm.pool.empty()) {
     *e = s->tm.pool.back();
@@ -299,7 +307,7 @@ mdpl_status launch_force(mdpl_sim* s, const double* x, const double* y, const do
   out.track = s->track;
   if (!out.fuse) out.track.ring = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (s->timing && timing_slot >= 0) {
+  if (timed_launch(s, timing_slot)) {
     HIP_TRY(take_event(s, &e0));
     HIP_TRY(take_event(s, &e1));
     HIP_TRY(hipEventRecord(e0, s->st));
@@ -589,9 +597,11 @@ mdpl_status mdpl_clear_flags(mdpl_sim* s) {
   return MDPL_OK;
 }
 
-mdpl_status mdpl_set_timing(mdpl_sim* s, int32_t on) {
-  if (!s || on < 0) return MDPL_EINVAL;
+mdpl_status mdpl_set_timing(mdpl_sim* s, int32_t on, int32_t every) {
+  if (!s || on < 0 || every < 1) return MDPL_EINVAL;
   s->timing = on != 0;
+  s->tm.every = every;
+  s->tm.launches[0] = s->tm.launches[1] = 0;
   // reserve event pairs so that no event is created while timing
   const size_t want = on > 1 ? 4 * (size_t)on : 0;
   while (s->tm.pool.size() < want) {
@@ -616,6 +626,7 @@ mdpl_status mdpl_kernel_time(mdpl_sim* s, int32_t which, double* ms, int64_t* la
   if (launches) *launches = (int64_t)(v.size() / 2);
   for (hipEvent_t e : v) s->tm.pool.push_back(e);
   v.clear();
+  s->tm.launches[which] = 0;
   return MDPL_OK;
 }
 
@@ -1246,7 +1257,7 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
                   [&](const StateArrays& cur, bool en, double* pe_w, int slot, bool,
                       double* const*, double*, double* disp) -> mdpl_status {
                     hipEvent_t e0 = nullptr, e1 = nullptr;
-                    if (s->timing && slot >= 0) {
+                    if (timed_launch(s, slot)) {
                       HIP_TRY(take_event(s, &e0));
                       HIP_TRY(take_event(s, &e1));
                       HIP_TRY(hipEventRecord(e0, s->st));

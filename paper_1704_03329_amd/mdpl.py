@@ -79,7 +79,7 @@ _SIGS = {
     "mdpl_rebuild_stats": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)], _I32),
     "mdpl_check": ([_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_I32)], _I32),
     "mdpl_clear_flags": ([_P], _I32),
-    "mdpl_set_timing": ([_P, _I32], _I32),
+    "mdpl_set_timing": ([_P, _I32, _I32], _I32),
     "mdpl_kernel_time": ([_P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I32),
     "mdpl_analysis_workspace_bytes": ([_I64, ctypes.POINTER(_D), _D, _I32, ctypes.POINTER(_SZ)], _I32),
     "mdpl_boa": ([_P, _P, _P, _I64, ctypes.POINTER(_D), _D, _P, _P, _P, _P, _P, _SZ, _P], _I32),
@@ -247,10 +247,11 @@ def mdpl_clear_flags(sim: int):
     _check(lib().mdpl_clear_flags(sim), "mdpl_clear_flags")
 
 
-def mdpl_set_timing(sim: int, on, reserve: int = 0):
+def mdpl_set_timing(sim: int, on, reserve: int = 0, every: int = 1):
     """on: bool; reserve: launches to create events for up front (none are
-    then created while a timed run is enqueued)."""
-    _check(lib().mdpl_set_timing(sim, (max(int(reserve), 2) if reserve else 1) if on else 0),
+    then created while a timed run is enqueued); every: time launches 0,
+    every, 2 every, ... of each force kernel."""
+    _check(lib().mdpl_set_timing(sim, (max(int(reserve), 2) if reserve else 1) if on else 0, int(every)),
            "mdpl_set_timing")
 
 
