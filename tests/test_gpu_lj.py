@@ -308,6 +308,41 @@ def test_run_deterministic_and_resumable():
         assert torch.equal(state[k], s1[k]), k
 
 
+def test_launch_timing_stride():
+    """mdpl_set_timing(on, every): launches 0, every, 2 every, ... of each
+    force kernel are timed; timing does not change the trajectory."""
+    from paper_1704_03329_amd import mdpl as C
+
+    d = mdinputs.lj_fluid(10, temperature=1.0, seed=2)
+    box = d["box"]
+    mk = lambda: _sim(1000, box, rc=2.5, skin=0.3, reuse_every=10, precision="fp32")
+    ref, _ = _run(mk(), d["pos"], d["vel"], 20, 10)
+    sim = mk()
+    state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    counts = None
+    for every in (1, 8, 30):
+        C.mdpl_set_timing(sim.handle, True, reserve=32, every=every)
+        sim.run(state, 20, 10)
+        ms0, n0 = C.mdpl_kernel_time(sim.handle, 0)
+        ms1, n1 = C.mdpl_kernel_time(sim.handle, 1)
+        if counts is None:  # every launch of each kind
+            counts = (n0, n1)
+            assert n0 >= 17 and n1 >= 2, counts
+        assert (n0, n1) == tuple(-(-c // every) for c in counts), (every, n0, n1, counts)
+        assert ms0 > 0.0 and ms1 > 0.0
+        state = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    C.mdpl_set_timing(sim.handle, False)
+    sim.run(state, 20, 10)
+    C.mdpl_set_timing(sim.handle, True, every=3)
+    state2 = sim.new_state(torch.from_numpy(d["pos"]), torch.from_numpy(d["vel"]))
+    sim.run(state2, 20, 10)
+    torch.cuda.synchronize()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert torch.equal(state2[k], ref[k]), k
+    with pytest.raises(C.MdplError):
+        C.mdpl_set_timing(sim.handle, True, every=0)
+
+
 def test_run_continue_bitwise():
     """MDPL_RUN_CONTINUE: runs that go on from the last run's state (no
     rebinning, no F(r0) pass, the rebuild schedule carried over) give the
