@@ -65,7 +65,22 @@ __device__ __forceinline__ bf16x8 load8_strided(const unsigned short* p, int str
   return __builtin_bit_cast(bf16x8, w);
 }
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// sigmoid with the hardware reciprocal (about 1 ulp; the network's BF16
+// operands dominate its error)
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+// Sum over the 16 lanes of a DPP row (the lanes 16 g .. 16 g + 15): the
+// quads by lane ^ 1 and lane ^ 2, then the row's four quad sums by
+// rotations of 4 and 8 lanes.  Every lane receives the row sum; lanes of
+// quads 0 and 2 and of quads 1 and 3 pair the quad sums differently, so the
+// two groups can differ in the last bit.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);  // row_ror:4
+  v += dpp_move<0x128>(v);  // row_ror:8
+  return v;
+}
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -109,6 +124,19 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
     w3c[nt] = bf2f(a.w3[nt * 16 + col]);
   }
   const float b3 = a.b3[0];
+  // reciprocals of the feature scales this lane uses: its eight layer-1
+  // inputs (8 grp + k), and the features col and 16 + col of the gradients
+  float isd8[8], isd2[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int f = 8 * grp + k;
+    isd8[k] = f < kNIn ? 1.0f / a.sd[f] : 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int f = j * 16 + col;
+    isd2[j] = f < kNIn ? 1.0f / a.sd[f] : 0.0f;
+  }
 
   // TRAIN accumulators
   f32x4 gW2[4][4], gW1[4][2];
@@ -137,7 +165,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int f = 8 * grp + k;
-      gv[k] = (rok && f < kNIn) ? (a.G[ia * kNIn + f] - a.mu[f]) / a.sd[f] : 0.0f;
+      gv[k] = (rok && f < kNIn) ? (a.G[ia * kNIn + f] - a.mu[f]) * isd8[k] : 0.0f;
     }
     const bf16x8 A1 = pack8(gv);
     f32x4 z1[4], h1[4];
@@ -176,11 +204,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
     }
     // sum over the 16 columns held by the lanes of this group
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) ypart[r] += __shfl_xor(ypart[r], off, 64);
-      ypart[r] += b3;
-    }
+    for (int r = 0; r < 4; ++r) ypart[r] = row16_sum(ypart[r]) + b3;
     // ---- upstream gradient dL/dy (TRAIN) or dy/dy = 1 (EVAL)
     float dy[4];
 #pragma unroll
@@ -276,7 +300,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
           const int64_t row = r0 + 4 * grp + r;
           const bool ok = row < a.n && f < kNIn;
           const int64_t ir = ok ? (a.index ? (int64_t)a.index[row] : row) : 0;
-          gd[j][r] = ok ? (a.G[ir * kNIn + f] - a.mu[f]) / a.sd[f] : 0.0f;
+          gd[j][r] = ok ? (a.G[ir * kNIn + f] - a.mu[f]) * isd2[j] : 0.0f;
         }
       }
 #pragma unroll
@@ -316,7 +340,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(D1[1], W1b[nt][1], acc, 0, 0, 0);
       const int f = nt * 16 + col;
       if (f < kNIn) {
-        const float sc = a.e_sd / a.sd[f];
+        const float sc = a.e_sd * isd2[nt];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t row = r0 + 4 * grp + r;
