@@ -162,8 +162,10 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
         const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (!(d2 < rc2)) continue;
-        const float r = sqrtf((float)d2);
-        const float ir = 1.0f / r;
+        // 1/r from the hardware reciprocal square root (about 1 ulp), r = d2/r
+        const float d2f = (float)d2;
+        const float ir = __builtin_amdgcn_rsqf(d2f);
+        const float r = d2f * ir;
         const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
         const float fc = 0.5f * (__builtin_amdgcn_cosf(r * half_rev) + 1.0f);  // cos(pi r / rc)
         float eb[kNRad];
@@ -266,10 +268,10 @@ __device__ __forceinline__ void adjoint_coef(const float* __restrict__ d,
 }
 
 // dE/du for a centre with adjoint coefficients K and neighbour vector u
-// (length r, unit vector uh), accumulated into (gx, gy, gz).
-__device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, float ux, float uy,
-                                          float uz, float fc, float dfc, float& gx, float& gy,
-                                          float& gz) {
+// (length r, 1/r = ir, unit vector uh), accumulated into (gx, gy, gz).
+__device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, float ir, float ux,
+                                          float uy, float uz, float fc, float dfc, float& gx,
+                                          float& gy, float& gz) {
   float P[15], c[5], sn[5];
   legendre_d(uz, P);
   cpow(ux, uy, c, sn);
@@ -310,7 +312,7 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
       }
     }
     const float dot = ux * px + uy * py + uz * pz;
-    const float tw = w / r;
+    const float tw = w * ir;
     const float sc = dw * phi + K[50 + e] * w * dw;
     ax += sc * ux + tw * (px - dot * ux);
     ay += sc * uy + tw * (py - dot * uy);
@@ -379,13 +381,15 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
         const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (!(d2 < rc2)) continue;
-        const float r = sqrtf((float)d2);
-        const float ir = 1.0f / r;
+        // 1/r from the hardware reciprocal square root (about 1 ulp), r = d2/r
+        const float d2f = (float)d2;
+        const float ir = __builtin_amdgcn_rsqf(d2f);
+        const float r = d2f * ir;
         const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
         const float fc = 0.5f * (__builtin_amdgcn_cosf(r * half_rev) + 1.0f);
         const float dfc = -0.5f * pi_rc * __builtin_amdgcn_sinf(r * half_rev);
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-        pair_grad(Ki, r, ux, uy, uz, fc, dfc, gx, gy, gz);
+        pair_grad(Ki, r, ir, ux, uy, uz, fc, dfc, gx, gy, gz);
         fx += gx;
         fy += gy;
         fz += gz;
