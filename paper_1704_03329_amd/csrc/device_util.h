@@ -75,6 +75,14 @@ __device__ __forceinline__ double dpp_move(double v) {
                           dpp_i32<CTRL, ROWS>(__double2loint(v)));
 }
 
+__device__ __forceinline__ float readlane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double readlane63(double v) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
 // Largest value over the 64 lanes of a wave (all active), for values >= 0:
 // a running maximum within each row of 16 lanes, then across rows; lane 63
 // ends with the wave's maximum, which is returned to every lane.
@@ -96,19 +104,26 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
   o = dpp_move<0x118>(v); v = o > v ? o : v;
   o = dpp_move<0x142, 0xa>(v); v = o > v ? o : v;
   o = dpp_move<0x143, 0xc>(v); v = o > v ? o : v;
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
-                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+  return readlane63(v);
 }
 
+// Sum over the 64 lanes of a wave (all active) in a fixed order, on DPP:
+// the quads by lane ^ 1 and lane ^ 2, the rows of 16 by rotations of 4 and
+// 8 lanes, then the rows into lane 63 by the two row broadcasts; the total
+// is returned to every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);       // row_ror:4
+  v += dpp_move<0x128>(v);       // row_ror:8
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return readlane63(v);
 }
 
 // Sum over a 256-thread block; the result is valid in thread 0.  Fixed
-// order (wave butterflies, then the four wave sums pairwise).
+// order (the wave sums above, then the four wave sums pairwise).
 __device__ __forceinline__ double block_sum256(double v, double* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -121,11 +136,7 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 }
 
 __device__ __forceinline__ double block_max256(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(v, off, 64);
-    v = o > v ? o : v;
-  }
+  v = wave_max_nonneg(v);  // callers pass values >= 0
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) sh[wave] = v;
   __syncthreads();
