@@ -486,7 +486,7 @@ def main():
         fe_ms, fe_n = C.mdpl_kernel_time(sim.handle, 1)
         C.mdpl_set_timing(sim.handle, False)
         entries = C.mdpl_nlist_entries(sim.handle) if pairs != "cells" else 0
-        if not melted:
+        if not melted and not args.no_cpu_baseline:
             melted["pos"] = torch.stack([state["x"], state["y"], state["z"]], 1).cpu().numpy()
             melted["vel"] = torch.stack([state["vx"], state["vy"], state["vz"]], 1).cpu().numpy()
         log(f"elapsed {elapsed:.4f} s; force {f_ms / max(f_n, 1) * 1e3:.1f} us x {f_n}; "
