@@ -234,7 +234,44 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
 }
 
 // ------------------------------------------------------------- adjoint
-// K = (alpha/gamma for eta 0.5 [25], for eta 2 [25], delta_0, delta_1,
+// Phi of one eta regrouped by m: Phi = sum_m A_m(z) Re (x+iy)^m + B_m(z) Im (x+iy)^m
+// with A_m(z) = sum_{l>=m} alpha_lm P~_l^m(z) and B_m likewise with gamma.  The
+// coefficients of A_m and B_m in powers of z (those of the P~_l^m of
+// legendre_d collected per m) are stored per eta, 25 floats, as
+//   A_0[5] A_1[4] B_1[4] A_2[3] B_2[3] A_3[2] B_3[2] A_4 B_4   (constant term first).
+// One pair then costs a Horner value and derivative per polynomial instead of
+// the 15 (l, m) terms of each sum.
+__device__ __forceinline__ void zpoly_of(const float* __restrict__ al, float* __restrict__ zc) {
+  auto A = [&](int l, int m) { return al[m == 0 ? l * l : l * l + 2 * m - 1]; };
+  auto B = [&](int l, int m) { return al[l * l + 2 * m]; };
+  zc[0] = A(0, 0) - 0.5f * A(2, 0) + 0.375f * A(4, 0);
+  zc[1] = A(1, 0) - 1.5f * A(3, 0);
+  zc[2] = 1.5f * A(2, 0) - 3.75f * A(4, 0);
+  zc[3] = 2.5f * A(3, 0);
+  zc[4] = 4.375f * A(4, 0);
+  zc[5] = A(1, 1) - 1.5f * A(3, 1);
+  zc[6] = 3.0f * A(2, 1) - 7.5f * A(4, 1);
+  zc[7] = 7.5f * A(3, 1);
+  zc[8] = 17.5f * A(4, 1);
+  zc[9] = B(1, 1) - 1.5f * B(3, 1);
+  zc[10] = 3.0f * B(2, 1) - 7.5f * B(4, 1);
+  zc[11] = 7.5f * B(3, 1);
+  zc[12] = 17.5f * B(4, 1);
+  zc[13] = 3.0f * A(2, 2) - 7.5f * A(4, 2);
+  zc[14] = 15.0f * A(3, 2);
+  zc[15] = 52.5f * A(4, 2);
+  zc[16] = 3.0f * B(2, 2) - 7.5f * B(4, 2);
+  zc[17] = 15.0f * B(3, 2);
+  zc[18] = 52.5f * B(4, 2);
+  zc[19] = 15.0f * A(3, 3);
+  zc[20] = 105.0f * A(4, 3);
+  zc[21] = 15.0f * B(3, 3);
+  zc[22] = 105.0f * B(4, 3);
+  zc[23] = 105.0f * A(4, 4);
+  zc[24] = 105.0f * B(4, 4);
+}
+
+// K = (z-polynomials of Phi for eta 0.5 [25], for eta 2 [25], delta_0, delta_1,
 //      dE/dG_k for the 16 radial features) of one particle, from its dE/dG
 // (24) and moments (50); formed where the backward needs them.
 __device__ __forceinline__ void adjoint_coef(const float* __restrict__ d,
@@ -251,76 +288,102 @@ __device__ __forceinline__ void adjoint_coef(const float* __restrict__ d,
       b[l] = acc;
       bsum += acc;
     }
+    float al[kNMom];  // alpha_lm / gamma_lm in the moment layout
 #pragma unroll
     for (int l = 0; l <= 4; ++l) {
-      out[e * kNMom + l * l] = 2.0f * b[l] * mm[e * kNMom + l * l];
+      al[l * l] = 2.0f * b[l] * mm[e * kNMom + l * l];
 #pragma unroll
       for (int m = 1; m <= l; ++m) {
         const float w = 2.0f * omega(l * (l + 1) / 2 + m) * b[l];
-        out[e * kNMom + l * l + 2 * m - 1] = w * mm[e * kNMom + l * l + 2 * m - 1];
-        out[e * kNMom + l * l + 2 * m] = w * mm[e * kNMom + l * l + 2 * m];
+        al[l * l + 2 * m - 1] = w * mm[e * kNMom + l * l + 2 * m - 1];
+        al[l * l + 2 * m] = w * mm[e * kNMom + l * l + 2 * m];
       }
     }
+    zpoly_of(al, out + e * kNMom);
     out[50 + e] = -2.0f * bsum;
   }
 #pragma unroll
   for (int k = 0; k < kNRad; ++k) out[52 + k] = d[k];
 }
 
+// value v and derivative dv of c[0] + c[1] z + ... + c[D] z^D (Horner)
+template <int D>
+__device__ __forceinline__ void poly_vd(const float* __restrict__ c, float z, float& v, float& dv) {
+  v = c[D];
+  dv = 0.0f;
+  if (D == 0) return;
+  dv = v;
+  v = v * z + c[D - 1];
+#pragma unroll
+  for (int i = D - 2; i >= 0; --i) {
+    dv = dv * z + v;
+    v = v * z + c[i];
+  }
+}
+
 // dE/du for a centre with adjoint coefficients K and neighbour vector u
 // (length r, 1/r = ir, unit vector uh), accumulated into (gx, gy, gz).
+// With Phi in the z-polynomial form, grad Phi (of the polynomial in x, y, z) is
+//   d/dz: sum_m A_m' Re (x+iy)^m + B_m' Im (x+iy)^m,
+//   d/dx: sum_m m (A_m Re (x+iy)^(m-1) + B_m Im (x+iy)^(m-1)),
+//   d/dy: sum_m m (-A_m Im (x+iy)^(m-1) + B_m Re (x+iy)^(m-1)).
 __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, float ir, float ux,
                                           float uy, float uz, float fc, float dfc, float& gx,
                                           float& gy, float& gz) {
-  float P[15], c[5], sn[5];
-  legendre_d(uz, P);
-  cpow(ux, uy, c, sn);
-  float radial = 0.0f;  // scalar multiplying uh
+  // (x + i y)^m, m = 1..4, and (m + 1) times them for the x and y derivatives
+  const float c1 = ux, s1 = uy;
+  const float c2 = ux * ux - uy * uy, s2 = 2.0f * ux * uy;
+  const float c3 = c2 * ux - s2 * uy, s3 = c2 * uy + s2 * ux;
+  const float c4 = c3 * ux - s3 * uy, s4 = c3 * uy + s3 * ux;
+  const float h1 = 2.0f * c1, k1 = 2.0f * s1, h2 = 3.0f * c2, k2 = 3.0f * s2;
+  const float h3 = 4.0f * c3, k3 = 4.0f * s3;
+  // radial: sum_k dE/dG_k e_k (-2 eta_r (r - R_k) fc + dfc), R_k = 0.85 + 0.11 k,
+  //       = (dfc - 2 eta_r (r - 0.85) fc) S0 + 0.22 eta_r fc S1,
+  //   S0 = sum_k dE/dG_k e_k, S1 = sum_k k dE/dG_k e_k
   float eb[kNRad];
   radial_basis(r, eb);
+  float S0 = 0.0f, S1 = 0.0f;
 #pragma unroll
   for (int k = 0; k < kNRad; ++k) {
-    const float d = r - (0.85f + 0.11f * (float)k);
-    radial += K[52 + k] * eb[k] * (-2.0f * kEtaR * d * fc + dfc);
+    const float t = K[52 + k] * eb[k];
+    S0 += t;
+    S1 += (float)k * t;
   }
+  float S = (dfc - 2.0f * kEtaR * (r - 0.85f) * fc) * S0 + (0.22f * kEtaR) * fc * S1;
+  float Gx = 0.0f, Gy = 0.0f, Gz = 0.0f;
   const float g0 = exp_hw(-0.5f * r * r);
   const float gsq = g0 * g0;
-  float ax = 0.0f, ay = 0.0f, az = 0.0f;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const float eta = e ? 2.0f : 0.5f;
     const float ex = e ? gsq * gsq : g0;  // exp(-eta r^2)
     const float w = ex * fc;
     const float dw = ex * (-2.0f * eta * r * fc + dfc);
-    float phi = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
-#pragma unroll
-    for (int l = 0; l <= 4; ++l) {
-#pragma unroll
-      for (int m = 0; m <= l; ++m) {
-        const float al = K[e * kNMom + (m == 0 ? l * l : l * l + 2 * m - 1)];
-        const float ga = m == 0 ? 0.0f : K[e * kNMom + l * l + 2 * m];
-        const float p = P[l * (l + 1) / 2 + m];
-        const float pd = m < l ? P[l * (l + 1) / 2 + m + 1] : 0.0f;
-        const float v = al * c[m] + ga * sn[m];
-        phi += p * v;
-        pz += pd * v;
-        if (m > 0) {
-          const float fm = (float)m;
-          px += p * fm * (al * c[m - 1] + ga * sn[m - 1]);
-          py += p * fm * (-al * sn[m - 1] + ga * c[m - 1]);
-        }
-      }
-    }
+    const float* __restrict__ Z = K + e * kNMom;
+    float a0, da0, a1, da1, b1, db1, a2, da2, b2, db2, a3, da3, b3, db3;
+    poly_vd<4>(Z + 0, uz, a0, da0);
+    poly_vd<3>(Z + 5, uz, a1, da1);
+    poly_vd<3>(Z + 9, uz, b1, db1);
+    poly_vd<2>(Z + 13, uz, a2, da2);
+    poly_vd<2>(Z + 16, uz, b2, db2);
+    poly_vd<1>(Z + 19, uz, a3, da3);
+    poly_vd<1>(Z + 21, uz, b3, db3);
+    const float a4 = Z[23], b4 = Z[24];
+    const float phi = a0 + a1 * c1 + b1 * s1 + a2 * c2 + b2 * s2 + a3 * c3 + b3 * s3 + a4 * c4 + b4 * s4;
+    const float pz = da0 + da1 * c1 + db1 * s1 + da2 * c2 + db2 * s2 + da3 * c3 + db3 * s3;
+    const float px = a1 + a2 * h1 + b2 * k1 + a3 * h2 + b3 * k2 + a4 * h3 + b4 * k3;
+    const float py = b1 - a2 * k1 + b2 * h1 - a3 * k2 + b3 * h2 - a4 * k3 + b4 * h3;
+    // w' Phi uh + w (grad Phi - (uh . grad Phi) uh) / r + delta w w' uh
     const float dot = ux * px + uy * py + uz * pz;
     const float tw = w * ir;
-    const float sc = dw * phi + K[50 + e] * w * dw;
-    ax += sc * ux + tw * (px - dot * ux);
-    ay += sc * uy + tw * (py - dot * uy);
-    az += sc * uz + tw * (pz - dot * uz);
+    S += dw * (phi + K[50 + e] * w) - tw * dot;
+    Gx += tw * px;
+    Gy += tw * py;
+    Gz += tw * pz;
   }
-  gx += ax + radial * ux;
-  gy += ay + radial * uy;
-  gz += az + radial * uz;
+  gx += S * ux + Gx;
+  gy += S * uy + Gy;
+  gz += S * uz + Gz;
 }
 
 // ------------------------------------------------------------- backward
