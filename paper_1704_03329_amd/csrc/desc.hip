@@ -26,9 +26,9 @@
 // and F_a = sum_{j in N(a)} (dE_a/du_aj - dE_j/du_ja).  k_desc_bwd forms each
 // term g_ij = dE_i/du_ij once, with centre i's coefficients only, and
 // scatters it: + g_ij to particle i (a register sum) and - g_ij to
-// neighbour j (an FP32 LDS atomic on the tile slot, then one global atomic
-// per touched slot).  The order in which the atomics land varies from run to
-// run, so the last bits of the forces do too.
+// neighbour j (a 64-bit fixed-point LDS atomic on the tile slot, then one
+// global FP32 atomic per touched slot).  The order in which the global
+// atomics land varies from run to run, so the last bits of the forces do too.
 #include <math.h>
 
 #include "device_util.h"
@@ -390,12 +390,13 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
 // The term of pair (i, j) that involves centre i's coefficients,
 // g_ij = dE_i/du_ij, enters F_i with + and F_j with - (F_a = sum_j dE_a/du_aj
 // - dE_j/du_ja), so each thread needs only its own K_i: it adds g_ij to its
-// particle and subtracts it from the neighbour's LDS accumulator; the block
-// then adds its accumulators to the outputs with global atomics (the output
-// is zeroed first).  Two lanes share a particle, each taking every other
-// list word (twice the waves in flight; the 128-VGPR bound of 1024-thread
-// workgroups spills a few registers, which costs less than it gains).  FP32 atomics make the last bits of the forces depend on
-// the order in which blocks and waves land.
+// particle and subtracts it from the neighbour's LDS accumulator (64-bit
+// fixed point, see fix_of; a term too large for it goes to the output
+// directly); the block then adds its accumulators to the outputs with global
+// atomics (the output is zeroed first).  Two lanes share a particle, each
+// taking every other list word (twice the waves in flight).  The global FP32
+// atomics make the last bits of the forces depend on the order in which
+// blocks and waves land.
 __global__ void k_zero3(float* __restrict__ a, float* __restrict__ b, float* __restrict__ c,
                         int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -412,15 +413,15 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
                                                    const int32_t* __restrict__ cs, Grid g,
                                                    TileList tl, float rc, DescIO io) {
   __shared__ TileShared t;
-  __shared__ float acc[3][kTileMax];
+  __shared__ unsigned long long acc[3][kTileMax];
   const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
   const int nt = total < kTileCap ? total : kTileCap;
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
-    acc[0][u] = 0.0f;
-    acc[1][u] = 0.0f;
-    acc[2][u] = 0.0f;
+    acc[0][u] = 0;
+    acc[1][u] = 0;
+    acc[2][u] = 0;
   }
   tile_load<true>(g, x, y, z, total, t);  // ends with a barrier
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
@@ -456,9 +457,18 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
         fx += gx;
         fy += gy;
         fz += gz;
-        atomicAdd(&acc[0][u], -gx);
-        atomicAdd(&acc[1][u], -gy);
-        atomicAdd(&acc[2][u], -gz);
+        if (fix_fits(gx) && fix_fits(gy) && fix_fits(gz)) {
+          atomicAdd(&acc[0][u], fix_of(-(double)gx));
+          atomicAdd(&acc[1][u], fix_of(-(double)gy));
+          atomicAdd(&acc[2][u], fix_of(-(double)gz));
+        } else {
+          const int lo = t.cell[u];
+          const int sj = t.src[lo] + (u - t.prefix[lo]);
+          const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
+          unsafeAtomicAdd(&io.fx[oj], -gx);
+          unsafeAtomicAdd(&io.fy[oj], -gy);
+          unsafeAtomicAdd(&io.fz[oj], -gz);
+        }
       }
     }
     unsafeAtomicAdd(&io.fx[oi], fx);
@@ -470,8 +480,9 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
     const int lo = t.cell[u];  // tile cell of u (slot map filled by tile_load)
     const int sj = t.src[lo] + (u - t.prefix[lo]);
     const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
-    const float ax = acc[0][u], ay = acc[1][u], az = acc[2][u];
-    if (ax != 0.0f || ay != 0.0f || az != 0.0f) {
+    const unsigned long long qx = acc[0][u], qy = acc[1][u], qz = acc[2][u];
+    if (qx | qy | qz) {
+      const float ax = (float)fix_value(qx), ay = (float)fix_value(qy), az = (float)fix_value(qz);
       unsafeAtomicAdd(&io.fx[oj], ax);
       unsafeAtomicAdd(&io.fy[oj], ay);
       unsafeAtomicAdd(&io.fz[oj], az);

@@ -5,6 +5,20 @@
 
 namespace mdpl {
 
+// LDS reaction accumulators in 64-bit fixed point, units of 2^-32: FP32
+// atomic adds in LDS run one lane at a time on this chip (about 3 cycles per
+// active lane, some 40 times the cost of an integer add), while integer sums
+// are also exact and independent of their order.  A value must satisfy
+// fix_fits (|v| < 2^30, false for inf and NaN) to go through them.
+constexpr double kFixUnit = 4294967296.0;  // 2^32 per unit
+__device__ __forceinline__ bool fix_fits(double v) { return __builtin_fabs(v) < 1073741824.0; }
+__device__ __forceinline__ unsigned long long fix_of(double v) {
+  return (unsigned long long)(long long)(v * kFixUnit);
+}
+__device__ __forceinline__ double fix_value(unsigned long long a) {
+  return (double)(long long)a * (1.0 / kFixUnit);
+}
+
 // Fold a coordinate into [0, L): x - L floor(x / L), each operation rounded
 // (no contraction), then one correction step against rounding to L.
 __device__ __forceinline__ double fold(double x, double L) {

@@ -27,12 +27,9 @@ namespace mdpl {
 template <typename MT>
 struct HalfAcc {  // LDS accumulator of the reactions (see above)
   using T = unsigned long long;
-  static constexpr double kUnit = 4294967296.0;  // 2^32 per force unit
-  static __device__ __forceinline__ bool fits(double v) { return __builtin_fabs(v) < 1073741824.0; }
-  static __device__ __forceinline__ void add(T* a, double v) {
-    atomicAdd(a, (T)(long long)(v * kUnit));
-  }
-  static __device__ __forceinline__ double get(T a) { return (double)(long long)a * (1.0 / kUnit); }
+  static __device__ __forceinline__ bool fits(double v) { return fix_fits(v); }
+  static __device__ __forceinline__ void add(T* a, double v) { atomicAdd(a, fix_of(v)); }
+  static __device__ __forceinline__ double get(T a) { return fix_value(a); }
 };
 template <>
 struct HalfAcc<double> {
