@@ -394,9 +394,15 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
 // fixed point, see fix_of; a term too large for it goes to the output
 // directly); the block then adds its accumulators to the outputs with global
 // atomics (the output is zeroed first).  Two lanes share a particle, each
-// taking every other list word (twice the waves in flight).  The global FP32
-// atomics make the last bits of the forces depend on the order in which
-// blocks and waves land.
+// taking every other list word (twice the waves in flight).  Separations come
+// from the FP32 tile-centred coordinates of the LJ force pass (about 1e-7 of
+// a separation; the terms vanish smoothly at rc, so a pair that an FP32 test
+// decides differently from an FP64 one changes nothing measurable).  A lane
+// first marks its in-range entries in a bit mask and then walks the set bits
+// only, so the wave's trips follow the in-range counts (the skin's entries
+// and the ragged ends of the lists no longer idle lanes through whole pair
+// terms).  The global FP32 atomics make the last bits of the forces depend on
+// the order in which blocks and waves land.
 __global__ void k_zero3(float* __restrict__ a, float* __restrict__ b, float* __restrict__ c,
                         int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -412,44 +418,72 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
                                                    const double* __restrict__ z,
                                                    const int32_t* __restrict__ cs, Grid g,
                                                    TileList tl, float rc, DescIO io) {
-  __shared__ TileShared t;
+  __shared__ TileF32 t;
+  __shared__ uint16_t home[kBrickMax];
   __shared__ unsigned long long acc[3][kTileMax];
   const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
-  const int nt = total < kTileCap ? total : kTileCap;
+  const int ntc = (g.B[0] + 2) * (g.B[1] + 2) * (g.B[2] + 2);
+  const int nt = total < TileF32::kCap ? total : TileF32::kCap;
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
     acc[0][u] = 0;
     acc[1][u] = 0;
     acc[2][u] = 0;
   }
-  tile_load<true>(g, x, y, z, total, t);  // ends with a barrier
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
-  const double rc2 = (double)rc * (double)rc;
+  double ox, oy, oz;
+  tile_centre(g, brick, ox, oy, oz);
+  tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);  // ends with a barrier
+  const float rc2 = rc * rc;
   const float pi_rc = 3.14159265358979f / rc;
   const float half_rev = 0.5f / rc;
   const int part = (int)threadIdx.x & 1;  // two lanes per particle, alternate list words
   for (int s = s0 + ((int)threadIdx.x >> 1); s < s1; s += (int)(blockDim.x >> 1)) {
-    const double xi = x[s], yi = y[s], zi = z[s];
+    // FP32 coordinates relative to the tile centre (the force pass's), own
+    // position from the particle's own slot
+    const int hs = s - s0 < kBrickMax ? home[s - s0] : TileF32::kDummy;
+    const float xi = t.px[hs], yi = t.py[hs], zi = t.pz[hs];
     const int64_t oi = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
     float Ki[68];
     adjoint_coef(io.dEdG + oi * kNFeat, io.mom + oi * (2 * kNMom), Ki);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     const int ng = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
-    for (int gi = part; gi < ng; gi += 2) {
-      const uint64_t word = col[(int64_t)gi * tl.stride];
-      for (int q = 0; q < 4; ++q) {
-        const int u = (int)((word >> (16 * q)) & 0xffff) >> kFullShift;
-        if (u >= nt) continue;  // padding slot
-        const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        if (!(d2 < rc2)) continue;
+    const int nw = ng > part ? (ng - part + 1) >> 1 : 0;  // this lane's words: part + 2 w
+    for (int w0 = 0; w0 < nw; w0 += 16) {
+      // the in-range entries of up to 16 words as a bit mask (bit 4 w + q:
+      // entry q of word w0 + w), so that the pair terms below run on the
+      // lanes' in-range entries only, not on every entry of the list
+      const int wn = nw - w0 < 16 ? nw - w0 : 16;
+      uint64_t mask = 0;
+      for (int w = 0; w < wn; ++w) {
+        const uint64_t word = col[(int64_t)(part + 2 * (w0 + w)) * tl.stride];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int u = (int)((word >> (16 * q)) & 0xffff) >> kFullShift;
+          u = u < nt ? u : TileF32::kDummy;  // padding: the far-away dummy slot
+          const float dx = t.px[u] - xi, dy = t.py[u] - yi, dz = t.pz[u] - zi;
+          const float d2 = dx * dx + dy * dy + dz * dz;
+          if (d2 < rc2) mask |= 1ull << (4 * w + q);
+        }
+      }
+      // one in-range entry per lane and trip; the word of the next one is
+      // loaded a trip ahead
+      int b = mask ? __builtin_ctzll(mask) : 64;
+      uint64_t word = b < 64 ? col[(int64_t)(part + 2 * (w0 + (b >> 2))) * tl.stride] : 0;
+      while (b < 64) {
+        mask &= mask - 1;
+        const int nb = mask ? __builtin_ctzll(mask) : 64;
+        const uint64_t nword =
+            nb < 64 ? col[(int64_t)(part + 2 * (w0 + (nb >> 2))) * tl.stride] : 0;
+        const int u = (int)((word >> (16 * (b & 3))) & 0xffff) >> kFullShift;
+        const float dx = t.px[u] - xi, dy = t.py[u] - yi, dz = t.pz[u] - zi;
+        const float d2 = dx * dx + dy * dy + dz * dz;
         // 1/r from the hardware reciprocal square root (about 1 ulp), r = d2/r
-        const float d2f = (float)d2;
-        const float ir = __builtin_amdgcn_rsqf(d2f);
-        const float r = d2f * ir;
-        const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
+        const float ir = __builtin_amdgcn_rsqf(d2);
+        const float r = d2 * ir;
+        const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
         const float fc = 0.5f * (__builtin_amdgcn_cosf(r * half_rev) + 1.0f);
         const float dfc = -0.5f * pi_rc * __builtin_amdgcn_sinf(r * half_rev);
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
@@ -457,18 +491,20 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
         fx += gx;
         fy += gy;
         fz += gz;
-        if (fix_fits(gx) && fix_fits(gy) && fix_fits(gz)) {
+        if (fix_fits((double)(__builtin_fabsf(gx) + __builtin_fabsf(gy) + __builtin_fabsf(gz)))) {
           atomicAdd(&acc[0][u], fix_of(-(double)gx));
           atomicAdd(&acc[1][u], fix_of(-(double)gy));
           atomicAdd(&acc[2][u], fix_of(-(double)gz));
         } else {
-          const int lo = t.cell[u];
+          const int lo = tile_cell_of(t, ntc, u);
           const int sj = t.src[lo] + (u - t.prefix[lo]);
           const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
           unsafeAtomicAdd(&io.fx[oj], -gx);
           unsafeAtomicAdd(&io.fy[oj], -gy);
           unsafeAtomicAdd(&io.fz[oj], -gz);
         }
+        b = nb;
+        word = nword;
       }
     }
     unsafeAtomicAdd(&io.fx[oi], fx);
@@ -477,11 +513,11 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
   }
   __syncthreads();
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
-    const int lo = t.cell[u];  // tile cell of u (slot map filled by tile_load)
-    const int sj = t.src[lo] + (u - t.prefix[lo]);
-    const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
     const unsigned long long qx = acc[0][u], qy = acc[1][u], qz = acc[2][u];
     if (qx | qy | qz) {
+      const int lo = tile_cell_of(t, ntc, u);
+      const int sj = t.src[lo] + (u - t.prefix[lo]);
+      const int64_t oj = io.perm ? (int64_t)io.perm[sj] : (int64_t)sj;
       const float ax = (float)fix_value(qx), ay = (float)fix_value(qy), az = (float)fix_value(qz);
       unsafeAtomicAdd(&io.fx[oj], ax);
       unsafeAtomicAdd(&io.fy[oj], ay);

@@ -9,11 +9,18 @@ namespace mdpl {
 // atomic adds in LDS run one lane at a time on this chip (about 3 cycles per
 // active lane, some 40 times the cost of an integer add), while integer sums
 // are also exact and independent of their order.  A value must satisfy
-// fix_fits (|v| < 2^30, false for inf and NaN) to go through them.
-constexpr double kFixUnit = 4294967296.0;  // 2^32 per unit
-__device__ __forceinline__ bool fix_fits(double v) { return __builtin_fabs(v) < 1073741824.0; }
+// fix_fits (|v| < 2^19, false for inf and NaN) to go through them; then
+// v 2^32 lies within 2^51 of zero, and adding 1.5 2^52 to it in FP64 rounds
+// it to an integer in the low bits of the sum (one FMA and a 64-bit
+// subtraction instead of a conversion to a 64-bit integer).
+constexpr double kFixUnit = 4294967296.0;    // 2^32 per unit
+constexpr double kFixMax = 524288.0;         // 2^19
+constexpr double kFixMagic = 6755399441055744.0;  // 1.5 2^52
+__device__ __forceinline__ bool fix_fits(double v) { return __builtin_fabs(v) < kFixMax; }
 __device__ __forceinline__ unsigned long long fix_of(double v) {
-  return (unsigned long long)(long long)(v * kFixUnit);
+  const double t = __builtin_fma(v, kFixUnit, kFixMagic);
+  return (unsigned long long)__double_as_longlong(t) -
+         (unsigned long long)__double_as_longlong(kFixMagic);
 }
 __device__ __forceinline__ double fix_value(unsigned long long a) {
   return (double)(long long)a * (1.0 / kFixUnit);

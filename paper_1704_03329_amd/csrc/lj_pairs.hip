@@ -22,7 +22,7 @@ namespace mdpl {
 // Accumulators: FP32 atomic adds in LDS are several times slower on this
 // chip than integer ones, so the FP32 pass sums the reactions as 64-bit
 // integers in units of 2^-32 (exact integer sums, finer than FP32); a pair
-// force component of 2^30 or more bypasses them and goes to the output
+// force component of 2^19 or more bypasses them and goes to the output
 // directly.  The FP64 pass sums in double.
 template <typename MT>
 struct HalfAcc {  // LDS accumulator of the reactions (see above)
