@@ -128,6 +128,18 @@ struct DescIO {
   float* fz;
 };
 
+// The lowest set bit of the 128-bit mask (m0, m1), cleared; 128 when none is
+// left.  Selects only, so that the masks stay in registers.
+__device__ __forceinline__ int next_bit(uint64_t& m0, uint64_t& m1) {
+  const bool lo = m0 != 0;
+  const uint64_t mm = lo ? m0 : m1;
+  const int b = mm ? __builtin_ctzll(mm) + (lo ? 0 : 64) : 128;
+  const uint64_t cl = mm & (mm - 1);
+  m0 = lo ? cl : m0;
+  m1 = lo ? m1 : cl;
+  return b;
+}
+
 // ------------------------------------------------------------- forward
 __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
                                                    const double* __restrict__ y,
@@ -138,6 +150,7 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
   const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
+  const int nt = total < TileShared::kCap ? total : TileShared::kCap;
   tile_load<true>(g, x, y, z, total, t);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const double rc2 = (double)rc * (double)rc;
@@ -155,13 +168,51 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
       for (int k = 0; k < kNMom; ++k) M[e][k] = 0.0f;
     const int ng = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
-    for (int gi = 0; gi < ng; ++gi) {
-      const uint64_t word = col[(int64_t)gi * tl.stride];
-      for (int q = 0; q < 4; ++q) {
-        const int u = (int)((word >> (16 * q)) & 0xffff) >> kFullShift;
+    for (int c0 = 0; c0 < ng; c0 += 32) {
+      // the in-range entries of up to 32 words as two bit masks (bit 4 w + q
+      // of m[w / 16]: entry q of word c0 + w); the terms below then run on
+      // the lanes' in-range entries only
+      const int wn = ng - c0 < 32 ? ng - c0 : 32;
+      uint64_t m0 = 0, m1 = 0;
+      for (int wg = 0; wg < wn; wg += 4) {
+        // four words in flight at once (rows past the lane's last word read
+        // its last word again and are ignored)
+        uint64_t wd[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          wd[k] = col[(int64_t)(c0 + (wg + k < wn ? wg + k : wn - 1)) * tl.stride];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int w = wg + k;
+          uint64_t bits = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            int u = (int)((wd[k] >> (16 * q)) & 0xffff) >> kFullShift;
+            u = u < nt ? u : TileShared::kDummy;  // padding: the far-away dummy slot
+            const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < rc2) bits |= 1ull << q;
+          }
+          if (w < wn) {
+            if (w < 16) m0 |= bits << (4 * w);
+            else m1 |= bits << (4 * (w - 16));
+          }
+        }
+      }
+      // one in-range entry per lane and trip; the word of the next one is
+      // loaded a trip ahead
+      // (the load goes to a valid row even when no bit is left)
+      int b = next_bit(m0, m1);
+      uint64_t word = col[(int64_t)(c0 + (b < 128 ? b >> 2 : 0)) * tl.stride];
+      while (b < 128) {
+        const int u = (int)((word >> (16 * (b & 3))) & 0xffff) >> kFullShift;
+        b = next_bit(m0, m1);
+        word = col[(int64_t)(c0 + (b < 128 ? b >> 2 : 0)) * tl.stride];
+        // keep the load here, a trip ahead of its use (no memory operation
+        // may move across this point)
+        asm volatile("" ::: "memory");
         const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
         const double d2 = dx * dx + dy * dy + dz * dz;
-        if (!(d2 < rc2)) continue;
         // 1/r from the hardware reciprocal square root (about 1 ulp), r = d2/r
         const float d2f = (float)d2;
         const float ir = __builtin_amdgcn_rsqf(d2f);
@@ -457,27 +508,38 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
       // lanes' in-range entries only, not on every entry of the list
       const int wn = nw - w0 < 16 ? nw - w0 : 16;
       uint64_t mask = 0;
-      for (int w = 0; w < wn; ++w) {
-        const uint64_t word = col[(int64_t)(part + 2 * (w0 + w)) * tl.stride];
+      for (int wg = 0; wg < wn; wg += 4) {
+        // four words in flight at once (rows past the lane's last word read
+        // its last word again and are ignored)
+        uint64_t wd[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          int u = (int)((word >> (16 * q)) & 0xffff) >> kFullShift;
-          u = u < nt ? u : TileF32::kDummy;  // padding: the far-away dummy slot
-          const float dx = t.px[u] - xi, dy = t.py[u] - yi, dz = t.pz[u] - zi;
-          const float d2 = dx * dx + dy * dy + dz * dz;
-          if (d2 < rc2) mask |= 1ull << (4 * w + q);
+        for (int k = 0; k < 4; ++k)
+          wd[k] = col[(int64_t)(part + 2 * (w0 + (wg + k < wn ? wg + k : wn - 1))) * tl.stride];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int w = wg + k;
+          uint64_t bits = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            int u = (int)((wd[k] >> (16 * q)) & 0xffff) >> kFullShift;
+            u = u < nt ? u : TileF32::kDummy;  // padding: the far-away dummy slot
+            const float dx = t.px[u] - xi, dy = t.py[u] - yi, dz = t.pz[u] - zi;
+            const float d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < rc2) bits |= 1ull << q;
+          }
+          mask |= w < wn ? bits << (4 * w) : 0;
         }
       }
       // one in-range entry per lane and trip; the word of the next one is
       // loaded a trip ahead
+      // (the load goes to a valid row even when no bit is left)
       int b = mask ? __builtin_ctzll(mask) : 64;
-      uint64_t word = b < 64 ? col[(int64_t)(part + 2 * (w0 + (b >> 2))) * tl.stride] : 0;
+      uint64_t word = col[(int64_t)(part + 2 * (w0 + (b < 64 ? b >> 2 : 0))) * tl.stride];
       while (b < 64) {
-        mask &= mask - 1;
-        const int nb = mask ? __builtin_ctzll(mask) : 64;
-        const uint64_t nword =
-            nb < 64 ? col[(int64_t)(part + 2 * (w0 + (nb >> 2))) * tl.stride] : 0;
         const int u = (int)((word >> (16 * (b & 3))) & 0xffff) >> kFullShift;
+        mask &= mask - 1;
+        b = mask ? __builtin_ctzll(mask) : 64;
+        word = col[(int64_t)(part + 2 * (w0 + (b < 64 ? b >> 2 : 0))) * tl.stride];
         const float dx = t.px[u] - xi, dy = t.py[u] - yi, dz = t.pz[u] - zi;
         const float d2 = dx * dx + dy * dy + dz * dz;
         // 1/r from the hardware reciprocal square root (about 1 ulp), r = d2/r
@@ -503,8 +565,6 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
           unsafeAtomicAdd(&io.fy[oj], -gy);
           unsafeAtomicAdd(&io.fz[oj], -gz);
         }
-        b = nb;
-        word = nword;
       }
     }
     unsafeAtomicAdd(&io.fx[oi], fx);
