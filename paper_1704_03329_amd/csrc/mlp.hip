@@ -88,6 +88,20 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The raw features 8 grp .. 8 grp + 7 of row 16 tile + col (zero past the
+// 24 features); ok: the row exists.
+__device__ __forceinline__ void load_features(const MlpArgs& a, int64_t tile, int64_t ntiles,
+                                              int col, int grp, float g[8], bool& ok) {
+  const int64_t ra = tile * 16 + col;
+  ok = tile < ntiles && ra < a.n;
+  const int64_t ia = ok ? (a.index ? (int64_t)a.index[ra] : ra) : 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int f = 8 * grp + k;
+    g[k] = (ok && f < kNIn) ? a.G[ia * kNIn + f] : 0.0f;
+  }
+}
+
 template <bool TRAIN>
 __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
   __shared__ float scratch[kMlpThreads / 64][16][kNH + 1];
@@ -155,18 +169,26 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
   const int64_t ntiles = (a.n + 15) >> 4;
   const int64_t wave_id = (int64_t)blockIdx.x * (kMlpThreads / 64) + wv;
   const int64_t nwaves = (int64_t)gridDim.x * (kMlpThreads / 64);
+  // this lane's eight layer-1 features of a tile's row col, raw (the next
+  // tile's are loaded while the current one is computed)
+  float mu8[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int f = 8 * grp + k;
+    mu8[k] = f < kNIn ? a.mu[f] : 0.0f;
+  }
+  float gnext[8];
+  bool oknext = false;
+  load_features(a, wave_id, ntiles, col, grp, gnext, oknext);
   for (int64_t tile = wave_id; tile < ntiles; tile += nwaves) {
     const int64_t r0 = tile * 16;
     // ---- layer 1: A fragment = standardised features of row r0 + col
-    const int64_t ra = r0 + col;
-    const bool rok = ra < a.n;
-    const int64_t ia = rok ? (a.index ? (int64_t)a.index[ra] : ra) : 0;
     float gv[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int f = 8 * grp + k;
-      gv[k] = (rok && f < kNIn) ? (a.G[ia * kNIn + f] - a.mu[f]) * isd8[k] : 0.0f;
-    }
+    for (int k = 0; k < 8; ++k) gv[k] = oknext ? (gnext[k] - mu8[k]) * isd8[k] : 0.0f;
+    load_features(a, tile + nwaves, ntiles, col, grp, gnext, oknext);
+    // keep those loads here, a tile ahead of their use
+    asm volatile("" ::: "memory");
     const bf16x8 A1 = pack8(gv);
     f32x4 z1[4], h1[4];
 #pragma unroll
@@ -397,9 +419,12 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(MlpArgs a) {
 }
 
 hipError_t mlp_eval(const MlpArgs& a, hipStream_t st) {
+  // two waves per SIMD that each take many tiles: the weight fragments a
+  // wave loads first are then reused over ~8 tiles at N = 262,144 (2048
+  // blocks, two tiles per wave: 61 us; 1024: 48; 512: 43)
   int64_t tiles = (a.n + 15) >> 4;
   int64_t blocks = (tiles + 3) / 4;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 512) blocks = 512;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_mlp<false>, dim3((unsigned)blocks), dim3(kMlpThreads), 0, st, a);
   return hipGetLastError();
