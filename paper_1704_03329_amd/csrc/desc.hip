@@ -16,7 +16,9 @@
 //   zeta = 4: a = (16/5, 32 lam/5, 32/7, 8 lam/5, 8/35).
 //
 // Moments are packed per eta as 25 floats, l = 0..4: C_l0 at l^2, C_lm at
-// l^2 + 2m - 1, S_lm at l^2 + 2m.
+// l^2 + 2m - 1, S_lm at l^2 + 2m.  The forward sums w z^k Re/Im (x+iy)^m
+// (k <= 4 - m, also 25 per eta) over the pairs and forms the moments from
+// them once per particle, with the coefficients of the P~_l^m.
 //
 // Backward (forces): with b_l = dE/dT_l, the adjoint coefficients
 //   alpha_lm = 2 om_lm b_l C_lm, gamma_lm = 2 om_lm b_l S_lm, delta = -2 sum_l b_l
@@ -76,36 +78,13 @@ __device__ __forceinline__ float omega(int idx) {
   return t[idx];
 }
 
-// P~_l^m(z) for l <= 4 (and 0 for m = l + 1 via the caller), index l(l+1)/2 + m
-__device__ __forceinline__ void legendre_d(float z, float P[15]) {
-  const float z2 = z * z;
-  P[0] = 1.0f;
-  P[1] = z;
-  P[2] = 1.0f;
-  P[3] = 1.5f * z2 - 0.5f;
-  P[4] = 3.0f * z;
-  P[5] = 3.0f;
-  P[6] = (2.5f * z2 - 1.5f) * z;
-  P[7] = 7.5f * z2 - 1.5f;
-  P[8] = 15.0f * z;
-  P[9] = 15.0f;
-  P[10] = (4.375f * z2 - 3.75f) * z2 + 0.375f;
-  P[11] = (17.5f * z2 - 7.5f) * z;
-  P[12] = 52.5f * z2 - 7.5f;
-  P[13] = 105.0f * z;
-  P[14] = 105.0f;
-}
-
-// (x + i y)^m, m = 0..4
-__device__ __forceinline__ void cpow(float x, float y, float c[5], float s[5]) {
-  c[0] = 1.0f;
-  s[0] = 0.0f;
-#pragma unroll
-  for (int m = 1; m < 5; ++m) {
-    c[m] = c[m - 1] * x - s[m - 1] * y;
-    s[m] = c[m - 1] * y + s[m - 1] * x;
-  }
-}
+// P~_l^m(z) = d^m P_l / dz^m for l <= 4, the polynomials behind the moment
+// and adjoint coefficients below:
+//   m = 0: 1, z, 1.5 z^2 - 0.5, 2.5 z^3 - 1.5 z, 4.375 z^4 - 3.75 z^2 + 0.375
+//   m = 1: 1, 3 z, 7.5 z^2 - 1.5, 17.5 z^3 - 7.5 z          (l = 1 .. 4)
+//   m = 2: 3, 15 z, 52.5 z^2 - 7.5                           (l = 2 .. 4)
+//   m = 3: 15, 105 z                                         (l = 3, 4)
+//   m = 4: 105                                               (l = 4)
 
 // a_l of (1 + lam c)^zeta times 2^(1-zeta), for angular feature index a
 // (a = zi*4 + li*2 + ei, zeta = (1,4)[zi], lam = (+1,-1)[li])
@@ -223,9 +202,15 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
         radial_basis(r, eb);
 #pragma unroll
         for (int k = 0; k < kNRad; ++k) G[k] += eb[k] * fc;
-        float P[15], c[5], sn[5];
-        legendre_d(uz, P);
-        cpow(ux, uy, c, sn);
+        // per eta the sums of w z^k Re/Im (x+iy)^m, k <= 4 - m (the moments
+        // follow from them by the coefficients of P~_l^m, once per particle)
+        const float z2 = uz * uz, z3 = z2 * uz, z4 = z2 * z2;
+        const float c2 = ux * ux - uy * uy, s2 = 2.0f * ux * uy;
+        const float c3 = c2 * ux - s2 * uy, s3 = c2 * uy + s2 * ux;
+        const float c4 = c3 * ux - s3 * uy, s4 = c3 * uy + s3 * ux;
+        const float q[kNMom] = {1.0f, uz,      z2,      z3, z4,      ux,      ux * uz, ux * z2, ux * z3,
+                                uy,   uy * uz, uy * z2, uy * z3, c2, c2 * uz, c2 * z2, s2,      s2 * uz,
+                                s2 * z2, c3, c3 * uz, s3, s3 * uz, c4, s4};
         const float g0 = exp_hw(-0.5f * r * r);
         const float g1 = (g0 * g0) * (g0 * g0);  // exp(-2 r^2)
         const float w0 = g0 * fc;
@@ -233,20 +218,44 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
         diag[0] += w0 * w0;
         diag[1] += w1 * w1;
 #pragma unroll
-        for (int l = 0; l <= 4; ++l) {
-#pragma unroll
-          for (int m = 0; m <= l; ++m) {
-            const float p = P[l * (l + 1) / 2 + m];
-            const int ic = m == 0 ? l * l : l * l + 2 * m - 1;
-            M[0][ic] += w0 * p * c[m];
-            M[1][ic] += w1 * p * c[m];
-            if (m > 0) {
-              M[0][ic + 1] += w0 * p * sn[m];
-              M[1][ic + 1] += w1 * p * sn[m];
-            }
-          }
+        for (int k = 0; k < kNMom; ++k) {
+          M[0][k] += w0 * q[k];
+          M[1][k] += w1 * q[k];
         }
       }
+    }
+    // z-power sums (order of q above) -> C_lm, S_lm in the moment layout
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const float* N = M[e];
+      float C[kNMom];
+      C[0] = N[0];
+      C[1] = N[1];
+      C[4] = 1.5f * N[2] - 0.5f * N[0];
+      C[9] = 2.5f * N[3] - 1.5f * N[1];
+      C[16] = 4.375f * N[4] - 3.75f * N[2] + 0.375f * N[0];
+      C[2] = N[5];                          // C_11
+      C[3] = N[9];                          // S_11
+      C[5] = 3.0f * N[6];                   // C_21
+      C[6] = 3.0f * N[10];                  // S_21
+      C[10] = 7.5f * N[7] - 1.5f * N[5];    // C_31
+      C[11] = 7.5f * N[11] - 1.5f * N[9];   // S_31
+      C[17] = 17.5f * N[8] - 7.5f * N[6];   // C_41
+      C[18] = 17.5f * N[12] - 7.5f * N[10]; // S_41
+      C[7] = 3.0f * N[13];                  // C_22
+      C[8] = 3.0f * N[16];                  // S_22
+      C[12] = 15.0f * N[14];                // C_32
+      C[13] = 15.0f * N[17];                // S_32
+      C[19] = 52.5f * N[15] - 7.5f * N[13]; // C_42
+      C[20] = 52.5f * N[18] - 7.5f * N[16]; // S_42
+      C[14] = 15.0f * N[19];                // C_33
+      C[15] = 15.0f * N[21];                // S_33
+      C[21] = 105.0f * N[20];               // C_43
+      C[22] = 105.0f * N[22];               // S_43
+      C[23] = 105.0f * N[23];               // C_44
+      C[24] = 105.0f * N[24];               // S_44
+#pragma unroll
+      for (int k = 0; k < kNMom; ++k) M[e][k] = C[k];
     }
     float T[2][5];
 #pragma unroll
@@ -287,8 +296,8 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
 // ------------------------------------------------------------- adjoint
 // Phi of one eta regrouped by m: Phi = sum_m A_m(z) Re (x+iy)^m + B_m(z) Im (x+iy)^m
 // with A_m(z) = sum_{l>=m} alpha_lm P~_l^m(z) and B_m likewise with gamma.  The
-// coefficients of A_m and B_m in powers of z (those of the P~_l^m of
-// legendre_d collected per m) are stored per eta, 25 floats, as
+// coefficients of A_m and B_m in powers of z (those of the P~_l^m in the
+// table above, collected per m) are stored per eta, 25 floats, as
 //   A_0[5] A_1[4] B_1[4] A_2[3] B_2[3] A_3[2] B_3[2] A_4 B_4   (constant term first).
 // One pair then costs a Horner value and derivative per polynomial instead of
 // the 15 (l, m) terms of each sum.
