@@ -338,8 +338,9 @@ mdpl_status mdpl_desc_fwd(mdpl_sim* sim, const double* x, const double* y, const
 
 /* Forces F_i = -dE/dr_i of E = sum_i E_i(G_i), from dEdG (n x 24, dE_i/dG_i)
  * and mom of mdpl_desc_fwd at the same positions.  fx, fy, fz: float,
- * caller order, overwritten.  The pair terms are summed with FP32 atomics,
- * so the last bits of the forces may differ between runs (the sum of all
+ * caller order, overwritten.  The pair terms are summed per tile in 64-bit
+ * fixed point and then added to the outputs with FP32 device atomics, so
+ * the last bits of the forces may differ between runs (the sum of all
  * forces stays zero to rounding). */
 mdpl_status mdpl_desc_bwd(mdpl_sim* sim, const double* x, const double* y, const double* z,
                           const float* dEdG, const float* mom, float* fx, float* fy, float* fz);
@@ -368,6 +369,21 @@ typedef struct {
  * (n x 24 floats) for features G (n x 24), on the BF16 matrix cores. */
 mdpl_status mdpl_mlp_fwd(const mdpl_mlp_weights* w, const float* G, int64_t n, float* energy,
                          float* dEdG, void* stream);
+
+/* One force evaluation of the learned potential at positions x, y, z (caller
+ * order) already built in sim (mdpl_build): mdpl_desc_fwd, mdpl_mlp_fwd and
+ * mdpl_desc_bwd in one call that gathers the positions once and clears the
+ * force outputs inside the descriptor pass (no separate clearing launch).
+ * ws: device workspace of mdpl_mlp_run_floats(n) floats (features, moments,
+ * energies, dE/dG; contents undefined afterwards).  energy: per-atom
+ * energies (n floats, nullable); fx, fy, fz: float, caller order,
+ * overwritten, with the run-to-run last-bit variation of mdpl_desc_bwd.
+ * The sim must use full neighbour lists (not half lists or the list-free
+ * loop).  Errors: MDPL_EINVAL (null argument, unsupported list mode),
+ * MDPL_ESTATE (no mdpl_build), MDPL_EWORKSPACE (ws too small). */
+mdpl_status mdpl_mlp_forces(mdpl_sim* sim, const mdpl_mlp_weights* w, const double* x,
+                            const double* y, const double* z, float* ws, int64_t ws_floats,
+                            float* energy, float* fx, float* fy, float* fz);
 
 /* Floats of scratch mdpl_mlp_train_grad needs for a batch of `batch` rows. */
 mdpl_status mdpl_mlp_train_floats(int64_t batch, int64_t* floats_host);

@@ -1185,6 +1185,31 @@ mdpl_status mdpl_mlp_fwd(const mdpl_mlp_weights* w, const float* G, int64_t n, f
   return MDPL_OK;
 }
 
+mdpl_status mdpl_mlp_forces(mdpl_sim* s, const mdpl_mlp_weights* w, const double* x,
+                            const double* y, const double* z, float* ws, int64_t ws_floats,
+                            float* energy, float* fx, float* fy, float* fz) {
+  if (!s || !mlp_ok(w) || !x || !y || !z || !ws || !fx || !fy || !fz || s->tl.half ||
+      s->tl.cells)
+    return MDPL_EINVAL;
+  if (!s->built) return MDPL_ESTATE;
+  const int64_t n = s->n;
+  if (ws_floats < (int64_t)kMlpRunFloats * n) return MDPL_EWORKSPACE;
+  float* G = ws;
+  float* mom = G + 24 * n;
+  float* e = mom + 50 * n;
+  float* dG = e + n;
+  HIP_TRY(gather_canonical(x, y, z, s->perm, s->skeys, n, s->g, s->sx, s->sy, s->sz, s->st));
+  HIP_TRY(desc_forward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm, G,
+                       mom, s->st, fx, fy, fz));
+  MlpArgs a = mlp_args(w, G, n);
+  a.energy = energy ? energy : e;
+  a.dEdG = dG;
+  HIP_TRY(mlp_eval(a, s->st));
+  HIP_TRY(desc_backward(s->sx, s->sy, s->sz, s->cell_start, s->g, s->tl, (float)s->p.rc, s->perm,
+                        dG, mom, n, fx, fy, fz, s->st, true));
+  return MDPL_OK;
+}
+
 mdpl_status mdpl_mlp_train_floats(int64_t batch, int64_t* floats) {
   if (batch <= 0 || !floats) return MDPL_EINVAL;
   *floats = (int64_t)mlp_train_waves(batch) * (kMlpParams + 1);
@@ -1263,14 +1288,15 @@ mdpl_status mdpl_run_mlp(mdpl_sim* s, const mdpl_mlp_weights* w, float* ws, int6
                       HIP_TRY(hipEventRecord(e0, s->st));
                     }
                     HIP_TRY(desc_forward(cur.x, cur.y, cur.z, s->cell_start, s->g, s->tl, rc,
-                                         nullptr, G, mom, s->st));
+                                         nullptr, G, mom, s->st, (float*)cur.fx, (float*)cur.fy,
+                                         (float*)cur.fz));
                     MlpArgs a = mlp_args(w, G, n);
                     a.energy = e;
                     a.dEdG = dG;
                     HIP_TRY(mlp_eval(a, s->st));
                     HIP_TRY(desc_backward(cur.x, cur.y, cur.z, s->cell_start, s->g, s->tl, rc,
                                           nullptr, dG, mom, n, (float*)cur.fx, (float*)cur.fy,
-                                          (float*)cur.fz, s->st));
+                                          (float*)cur.fz, s->st, true));
                     if (e1) {
                       HIP_TRY(hipEventRecord(e1, s->st));
                       s->tm.ev[slot].push_back(e0);

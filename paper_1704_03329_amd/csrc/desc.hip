@@ -102,7 +102,7 @@ struct DescIO {
   float* mom;              // n x 50 (forward output, nullable; backward input)
   const float* dEdG;       // n x 24 (backward input), caller order
   const int32_t* perm;     // slot -> caller index (nullable: identity)
-  float* fx;               // forces (backward output), caller order
+  float* fx;               // forces (backward output; cleared by the forward if given), caller order
   float* fy;
   float* fz;
 };
@@ -272,6 +272,11 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
       }
     }
     const int64_t o = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
+    if (io.fx) {  // the backward's outputs, cleared for its atomics
+      io.fx[o] = 0.0f;
+      io.fy[o] = 0.0f;
+      io.fz[o] = 0.0f;
+    }
     float* __restrict__ Go = io.G + o * kNFeat;
 #pragma unroll
     for (int k = 0; k < kNRad; ++k) Go[k] = G[k];
@@ -597,8 +602,9 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
 
 hipError_t desc_forward(const double* x, const double* y, const double* z,
                         const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
-                        const int32_t* perm, float* G, float* mom, hipStream_t st) {
-  DescIO io{G, mom, nullptr, perm, nullptr, nullptr, nullptr};
+                        const int32_t* perm, float* G, float* mom, hipStream_t st, float* fx,
+                        float* fy, float* fz) {
+  DescIO io{G, mom, nullptr, perm, fx, fy, fz};
   const unsigned threads = tl.threads < 512 ? tl.threads : 512;
   hipLaunchKernelGGL(k_desc_fwd, dim3(tile_grid(g)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);
@@ -608,9 +614,10 @@ hipError_t desc_forward(const double* x, const double* y, const double* z,
 hipError_t desc_backward(const double* x, const double* y, const double* z,
                          const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
                          const int32_t* perm, const float* dEdG, const float* mom, int64_t n,
-                         float* fx, float* fy, float* fz, hipStream_t st) {
+                         float* fx, float* fy, float* fz, hipStream_t st, bool zeroed) {
   DescIO io{nullptr, const_cast<float*>(mom), dEdG, perm, fx, fy, fz};
-  hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
+  if (!zeroed)
+    hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
   const unsigned threads = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
   hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid(g)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);

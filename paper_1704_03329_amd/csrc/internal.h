@@ -321,13 +321,16 @@ hipError_t cna_signatures(const NList& nl, const double* sx, const double* sy, c
 
 
 // Learned potential: descriptors (desc.hip) and dense layers (mlp.hip).
+// desc_forward also clears fx, fy, fz (caller order) when they are given, so
+// that a following desc_backward with zeroed = true needs no clearing launch.
 hipError_t desc_forward(const double* x, const double* y, const double* z,
                         const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
-                        const int32_t* perm, float* G, float* mom, hipStream_t st);
+                        const int32_t* perm, float* G, float* mom, hipStream_t st,
+                        float* fx = nullptr, float* fy = nullptr, float* fz = nullptr);
 hipError_t desc_backward(const double* x, const double* y, const double* z,
                          const int32_t* cell_start, const Grid& g, const TileList& tl, float rc,
                          const int32_t* perm, const float* dEdG, const float* mom, int64_t n,
-                         float* fx, float* fy, float* fz, hipStream_t st);
+                         float* fx, float* fy, float* fz, hipStream_t st, bool zeroed = false);
 
 struct MlpArgs;
 hipError_t mlp_eval(const MlpArgs& a, hipStream_t st);

@@ -323,6 +323,8 @@ _SIGS_MLP = {
     "mdpl_scale_velocities": ([ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_double, ctypes.c_void_p],
                               ctypes.c_int32),
     "mdpl_mlp_run_floats": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mdpl_mlp_forces": ([ctypes.c_void_p, ctypes.POINTER(mdpl_mlp_weights)] + [ctypes.c_void_p] * 4
+                        + [ctypes.c_int64] + [ctypes.c_void_p] * 4, ctypes.c_int32),
     "mdpl_run_mlp": ([ctypes.c_void_p, ctypes.POINTER(mdpl_mlp_weights), ctypes.c_void_p, ctypes.c_int64]
                      + [ctypes.c_void_p] * 10 + [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32],
                      ctypes.c_int32),
@@ -389,6 +391,11 @@ def mdpl_mlp_run_floats(n: int) -> int:
     out = ctypes.c_int64(0)
     _check(lib().mdpl_mlp_run_floats(int(n), ctypes.byref(out)), "mdpl_mlp_run_floats")
     return int(out.value)
+
+
+def mdpl_mlp_forces(sim, w: mdpl_mlp_weights, x, y, z, ws, energy, fx, fy, fz):
+    _check(lib().mdpl_mlp_forces(_handle(sim), ctypes.byref(w), _ptr(x), _ptr(y), _ptr(z), _ptr(ws), ws.numel(),
+                                 _ptr(energy), _ptr(fx), _ptr(fy), _ptr(fz)), "mdpl_mlp_forces")
 
 
 def mdpl_run_mlp(sim, w: mdpl_mlp_weights, ws, state: dict, nsteps: int, sample_every: int, thermo=None,

@@ -29,6 +29,7 @@ from .mdpl import (  # noqa: E402  (re-exported names of the C entry points)
     mdpl_force_error,
     MDPL_MLP_STD_SCRATCH,
     mdpl_mlp_bf16,
+    mdpl_mlp_forces,
     mdpl_mlp_fwd,
     mdpl_mlp_run_floats,
     mdpl_mlp_standardise,
@@ -126,17 +127,30 @@ class MLPPotential:
         return e, dG
 
     def buffers(self, n: int) -> dict:
-        """Device buffers of one force evaluation for n atoms."""
+        """Device buffers of one force evaluation for n atoms: the library's
+        workspace (features, moments, energies, dE/dG, in that order, with
+        views of each) and the forces."""
         def f32(*shape):
             return torch.empty(shape, dtype=torch.float32, device=self.device)
 
-        return {"G": f32(n, 24), "mom": f32(n, 50), "e": f32(n), "dG": f32(n, 24),
+        ws = f32(mdpl_mlp_run_floats(n))
+        return {"ws": ws, "G": ws[:24 * n].view(n, 24), "mom": ws[24 * n:74 * n].view(n, 50),
+                "e": ws[74 * n:75 * n], "dG": ws[75 * n:99 * n].view(n, 24),
                 "fx": f32(n), "fy": f32(n), "fz": f32(n)}
 
     def forces(self, sim: LJSim, x, y, z, buf: dict | None = None):
         """(per-atom energies, fx, fy, fz) for positions already built in sim:
         descriptors and their moments, network energies and dE/dG, then the
-        descriptor backward (a scatter of the pair terms)."""
+        descriptor backward (a scatter of the pair terms), in one library
+        call."""
+        n = sim.n
+        b = buf if buf is not None else self.buffers(n)
+        mdpl_mlp_forces(sim, self.weights(), x, y, z, b["ws"], b["e"], b["fx"], b["fy"], b["fz"])
+        return b["e"], b["fx"], b["fy"], b["fz"]
+
+    def forces_three_calls(self, sim: LJSim, x, y, z, buf: dict | None = None):
+        """forces() through the three separate entry points (descriptors,
+        network, backward)."""
         n = sim.n
         b = buf if buf is not None else self.buffers(n)
         mdpl_desc_fwd(sim, x, y, z, b["G"], b["mom"])

@@ -134,6 +134,41 @@ def test_mlp_forces_match_oracle(config):
     assert np.linalg.norm(F.sum(0)) <= 1e-4 * np.abs(F).sum()
 
 
+def test_fused_forces_match_three_calls(config):
+    """mdpl_mlp_forces (one call: positions gathered once, outputs cleared
+    inside the descriptor pass) against mdpl_desc_fwd + mdpl_mlp_fwd +
+    mdpl_desc_bwd on the same positions: identical energies (the same
+    kernels on the same inputs), forces equal up to the order of the FP32
+    device atomics; outputs that held garbage are overwritten; a workspace
+    below mdpl_mlp_run_floats(n) is refused."""
+    from paper_1704_03329_amd.mdpl import MdplError
+    from paper_1704_03329_amd.sim import soa
+    from paper_1704_03329_amd import potential as P
+
+    pos, box = config
+    n = pos.shape[0]
+    sim = _sim(n, box)
+    x, y, z = soa(torch.from_numpy(pos).cuda())
+    sim.build(x, y, z)
+    m = _model(P.descriptors(sim, torch.from_numpy(pos).cuda()),
+               torch.from_numpy(np.linspace(-6, -3, n)).cuda())
+    sim.build(x, y, z)
+    b3 = m.buffers(n)
+    e3, f3x, f3y, f3z = [t.clone() for t in m.forces_three_calls(sim, x, y, z, b3)]
+    b1 = m.buffers(n)
+    for k in ("fx", "fy", "fz"):
+        b1[k].fill_(1e30)
+    for _ in range(2):  # twice: the second call starts from the first's outputs
+        e1, f1x, f1y, f1z = m.forces(sim, x, y, z, b1)
+        assert torch.equal(e1, e3)
+        F1 = torch.stack([f1x, f1y, f1z], 1).double().cpu().numpy()
+        F3 = torch.stack([f3x, f3y, f3z], 1).double().cpu().numpy()
+        assert _rel(F1, F3) <= 1e-6
+    small = torch.empty(P.mdpl_mlp_run_floats(n) - 1, dtype=torch.float32, device="cuda")
+    with pytest.raises(MdplError):
+        P.mdpl_mlp_forces(sim, m.weights(), x, y, z, small, b1["e"], b1["fx"], b1["fy"], b1["fz"])
+
+
 def test_train_gradient_and_adam_match_oracle(config):
     from paper_1704_03329_amd import potential as P
 
