@@ -15,6 +15,12 @@
 // and (1 + lam c)^zeta = sum_l a_l P_l(c):  zeta = 1: a = (1, lam);
 //   zeta = 4: a = (16/5, 32 lam/5, 32/7, 8 lam/5, 8/35).
 //
+// Both passes take separations from the FP32 tile-centred coordinates of
+// the LJ force pass (within about 4e-7 of the FP64 ones for these tiles);
+// the features' error stays that of their FP32 arithmetic, about 5e-6 of
+// the outermost radial feature, and a pair decided differently at rc adds
+// nothing, as every term vanishes smoothly there.
+//
 // Moments are packed per eta as 25 floats, l = 0..4: C_l0 at l^2, C_lm at
 // l^2 + 2m - 1, S_lm at l^2 + 2m.  The forward sums w z^k Re/Im (x+iy)^m
 // (k <= 4 - m, also 25 per eta) over the pairs and forms the moments from
@@ -125,17 +131,21 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
                                                    const double* __restrict__ z,
                                                    const int32_t* __restrict__ cs, Grid g,
                                                    TileList tl, float rc, DescIO io) {
-  __shared__ TileShared t;
+  __shared__ TileF32 t;
+  __shared__ uint16_t home[kBrickMax];
   const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
   const int total = tile_cells(g, brick, cs, t);
-  const int nt = total < TileShared::kCap ? total : TileShared::kCap;
-  tile_load<true>(g, x, y, z, total, t);
+  const int nt = total < TileF32::kCap ? total : TileF32::kCap;
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
-  const double rc2 = (double)rc * (double)rc;
+  double ox, oy, oz;
+  tile_centre(g, brick, ox, oy, oz);
+  tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);  // ends with a barrier
+  const float rc2 = rc * rc;
   const float half_rev = 0.5f / rc;  // revolutions per unit r of cos(pi r / rc)
   for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
-    const double xi = x[s], yi = y[s], zi = z[s];
+    const int hs = s - s0 < kBrickMax ? home[s - s0] : TileF32::kDummy;
+    const float xi = t.px[hs], yi = t.py[hs], zi = t.pz[hs];
     float G[kNRad];
     float M[2][kNMom];
     float diag[2] = {0.0f, 0.0f};
@@ -167,9 +177,9 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             int u = (int)((wd[k] >> (16 * q)) & 0xffff) >> kFullShift;
-            u = u < nt ? u : TileShared::kDummy;  // padding: the far-away dummy slot
-            const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
-            const double d2 = dx * dx + dy * dy + dz * dz;
+            u = u < nt ? u : TileF32::kDummy;  // padding: the far-away dummy slot
+            const float dx = t.px[u] - xi, dy = t.py[u] - yi, dz = t.pz[u] - zi;
+            const float d2 = dx * dx + dy * dy + dz * dz;
             if (d2 < rc2) bits |= 1ull << q;
           }
           if (w < wn) {
@@ -190,13 +200,12 @@ __global__ __launch_bounds__(512) void k_desc_fwd(const double* __restrict__ x,
         // keep the load here, a trip ahead of its use (no memory operation
         // may move across this point)
         asm volatile("" ::: "memory");
-        const double dx = t.x[u] - xi, dy = t.y[u] - yi, dz = t.z[u] - zi;
-        const double d2 = dx * dx + dy * dy + dz * dz;
+        const float dx = t.px[u] - xi, dy = t.py[u] - yi, dz = t.pz[u] - zi;
+        const float d2f = dx * dx + dy * dy + dz * dz;
         // 1/r from the hardware reciprocal square root (about 1 ulp), r = d2/r
-        const float d2f = (float)d2;
         const float ir = __builtin_amdgcn_rsqf(d2f);
         const float r = d2f * ir;
-        const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
+        const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
         const float fc = 0.5f * (__builtin_amdgcn_cosf(r * half_rev) + 1.0f);  // cos(pi r / rc)
         float eb[kNRad];
         radial_basis(r, eb);
