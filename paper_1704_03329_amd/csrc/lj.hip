@@ -384,13 +384,15 @@ __device__ __forceinline__ V group_sum(V v, int T) {
 #endif
 constexpr int kPlainThreads = MDPL_PLAIN_THREADS;
 
-// Plain FP32 pass.  Phase 1: the pair loop of every particle of the brick
-// (its own coordinates from its tile slot) into LDS sums; the lanes of a
-// wave take the same number of trips, so the band test of an entry costs
-// one comparison and the flags of the wave are one scalar mask; a group with
-// an entry in the band walks its list again with the exact rule.  Phase 2: one
-// thread per particle stores the force or applies the fused kick-kick-drift,
-// so that none of the FP64 state of the kick is live in the pair loop.
+// Plain FP32 pass: the pair loop of every particle of the brick (its own
+// coordinates from its tile slot); the lanes of a wave take the same number
+// of trips, so the band test of an entry costs one comparison and the flags
+// of the wave are one scalar mask; a group with an entry in the band walks
+// its list again with the exact rule.  The group's first lane then stores
+// the force or applies the fused kick-kick-drift at once, so the kick's
+// memory traffic overlaps the pair loops of the other waves instead of
+// following them after a workgroup barrier (none of the FP64 state of the
+// kick is live in the pair loop).
 template <typename OT>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__ y,
@@ -398,7 +400,6 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
                         TileList tl, LJConst c, F32Const k, ForceOut out) {
   __shared__ TileF32 t;
   __shared__ uint16_t home[kBrickMax];
-  __shared__ float fs[3][kBrickMax];
   __shared__ double vred[16];
   if (out.fuse) kick_publish(out.track, vred);
   const int brick = brick_of_block(g);
@@ -413,6 +414,9 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
   double ox, oy, oz;
   tile_centre(g, brick, ox, oy, oz);
   tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);
+  double scale = out.scale;
+  if (out.scale_dev) scale *= *out.scale_dev;
+  double vmax2 = 0.0;
   // The wave's pass and its lanes per particle are the same for all its lanes
   // (blockDim and kGroupWidth are multiples of 64), so they live in scalar
   // registers; every lane of the wave takes the same number of trips (the
@@ -499,31 +503,21 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
     ay = group_sum(ay, T);
     az = group_sum(az, T);
     if (has && part == 0) {
-      fs[0][la] = ax;
-      fs[1][la] = ay;
-      fs[2][la] = az;
-    }
-  }
-  __syncthreads();
-  double scale = out.scale;
-  if (out.scale_dev) scale *= *out.scale_dev;
-  double vmax2 = 0.0;
-  for (int la = threadIdx.x; la < npart; la += blockDim.x) {
-    const int s = s0 + la;
-    // the kicks use the force as stored (rounded to OT), like k_vv
-    const OT fx = (OT)((double)fs[0][la] * scale);
-    const OT fy = (OT)((double)fs[1][la] * scale);
-    const OT fz = (OT)((double)fs[2][la] * scale);
-    if (out.fuse) {
-      double m2;
-      (void)fused_kick(out, s, x[s], y[s], z[s], out.vx[s], out.vy[s], out.vz[s], (double)fx,
-                       (double)fy, (double)fz, m2);
-      vmax2 = m2 > vmax2 ? m2 : vmax2;
-    } else {
-      const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
-      ((OT*)out.fx)[o] = fx;
-      ((OT*)out.fy)[o] = fy;
-      ((OT*)out.fz)[o] = fz;
+      // the kicks use the force as stored (rounded to OT), like k_vv
+      const OT fx = (OT)((double)ax * scale);
+      const OT fy = (OT)((double)ay * scale);
+      const OT fz = (OT)((double)az * scale);
+      if (out.fuse) {
+        double m2;
+        (void)fused_kick(out, s, x[s], y[s], z[s], out.vx[s], out.vy[s], out.vz[s], (double)fx,
+                         (double)fy, (double)fz, m2);
+        vmax2 = m2 > vmax2 ? m2 : vmax2;
+      } else {
+        const int64_t o = out.scatter ? (int64_t)out.scatter[s] : (int64_t)s;
+        ((OT*)out.fx)[o] = fx;
+        ((OT*)out.fy)[o] = fy;
+        ((OT*)out.fz)[o] = fz;
+      }
     }
   }
   if (out.fuse && out.track.ring) block_track(out.track, vmax2, vred);
