@@ -413,10 +413,6 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
   const int npart = s1 - s0 < kBrickMax ? s1 - s0 : kBrickMax;  // more: flagged by the build
   double ox, oy, oz;
   tile_centre(g, brick, ox, oy, oz);
-  tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);
-  double scale = out.scale;
-  if (out.scale_dev) scale *= *out.scale_dev;
-  double vmax2 = 0.0;
   // The wave's pass and its lanes per particle are the same for all its lanes
   // (blockDim and kGroupWidth are multiples of 64), so they live in scalar
   // registers; every lane of the wave takes the same number of trips (the
@@ -425,6 +421,28 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
   const int lane = (int)threadIdx.x & 63;
   const int wbase = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
   constexpr uint64_t kDummyWord = 0x0001000100010001ull * (uint64_t)(4 * TileF32::kDummy);
+  // the count and first list word of the wave's first pass, loaded before
+  // the tile so that their latency overlaps the tile's
+  int cnt0 = 0;
+  uint64_t word0 = 0;
+  {
+    const int p0 = (wbase / kGroupWidth) * (kGroupWidth >> 1);
+    if (p0 < npart) {
+      int m;
+      const int T = lane_pass_T(p0, npart, m);
+      const int tt = wbase % kGroupWidth + lane;
+      const int part = tt & (T - 1);
+      if (tt < m * T) {
+        const int s = s0 + p0 + tt / T;
+        cnt0 = tl.cnt[s];
+        if (4 * part < tl.max_nb) word0 = tl.nbr[s + (int64_t)part * tl.stride];
+      }
+    }
+  }
+  tile_load_f32(g, x, y, z, total, ox, oy, oz, s0, t, home);
+  double scale = out.scale;
+  if (out.scale_dev) scale *= *out.scale_dev;
+  double vmax2 = 0.0;
   for (int base = wbase;; base += blockDim.x) {
     const int p0 = (base / kGroupWidth) * (kGroupWidth >> 1);
     if (p0 >= npart) break;
@@ -438,7 +456,8 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
     const int s = s0 + la;
     const int hu = home[la];
     const float xi = t.px[hu], yi = t.py[hu], zi = t.pz[hu];
-    const int ngroups = has ? (tl.cnt[s] + 3) >> 2 : 0;
+    const bool first = base == wbase;
+    const int ngroups = has ? ((first ? cnt0 : tl.cnt[s]) + 3) >> 2 : 0;
     const int trips = ngroups > part ? (ngroups - part + T - 1) >> sh : 0;
     const int wtrips = wave_max_nonneg(trips);
     const uint64_t* __restrict__ col = tl.nbr + s;
@@ -466,7 +485,7 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
     // while this one's entries are computed
     const uint64_t* __restrict__ p = col + (int64_t)part * tl.stride;
     uint64_t next = 0;
-    if (trips > 0) next = *p;
+    if (trips > 0) next = first ? word0 : *p;
     for (int q = 0; q < wtrips; ++q) {
       // a lane past its own part reads the dummy slot (no force, no band)
       const uint64_t word = q < trips ? next : kDummyWord;
