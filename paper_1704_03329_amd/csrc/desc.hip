@@ -346,10 +346,10 @@ __device__ __forceinline__ void zpoly_of(const float* __restrict__ al, float* __
 }
 
 // K = (z-polynomials of Phi for eta 0.5 [25], for eta 2 [25], delta_0, delta_1,
-//      dE/dG_k for the 16 radial features) of one particle, from its dE/dG
-// (24) and moments (50); formed where the backward needs them.
+//      dE/dG_k for the 16 radial features, k dE/dG_k) of one particle, from its
+// dE/dG (24) and moments (50); formed where the backward needs them.
 __device__ __forceinline__ void adjoint_coef(const float* __restrict__ d,
-                                             const float* __restrict__ mm, float out[68]) {
+                                             const float* __restrict__ mm, float out[84]) {
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     float b[5];
@@ -377,7 +377,10 @@ __device__ __forceinline__ void adjoint_coef(const float* __restrict__ d,
     out[50 + e] = -2.0f * bsum;
   }
 #pragma unroll
-  for (int k = 0; k < kNRad; ++k) out[52 + k] = d[k];
+  for (int k = 0; k < kNRad; ++k) {
+    out[52 + k] = d[k];
+    out[68 + k] = (float)k * d[k];
+  }
 }
 
 // value v and derivative dv of c[0] + c[1] z + ... + c[D] z^D (Horner)
@@ -419,9 +422,8 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
   float S0 = 0.0f, S1 = 0.0f;
 #pragma unroll
   for (int k = 0; k < kNRad; ++k) {
-    const float t = K[52 + k] * eb[k];
-    S0 += t;
-    S1 += (float)k * t;
+    S0 = __builtin_fmaf(K[52 + k], eb[k], S0);
+    S1 = __builtin_fmaf(K[68 + k], eb[k], S1);
   }
   float S = (dfc - 2.0f * kEtaR * (r - 0.85f) * fc) * S0 + (0.22f * kEtaR) * fc * S1;
   float Gx = 0.0f, Gy = 0.0f, Gz = 0.0f;
@@ -468,7 +470,8 @@ __device__ __forceinline__ void pair_grad(const float* __restrict__ K, float r, 
 // fixed point, see fix_of; a term too large for it goes to the output
 // directly); the block then adds its accumulators to the outputs with global
 // atomics (the output is zeroed first).  Two lanes share a particle, each
-// taking every other list word (twice the waves in flight).  Separations come
+// taking every other list word (512-thread workgroups: room for the 84
+// coefficients in registers without spills).  Separations come
 // from the FP32 tile-centred coordinates of the LJ force pass (about 1e-7 of
 // a separation; the terms vanish smoothly at rc, so a pair that an FP32 test
 // decides differently from an FP64 one changes nothing measurable).  A lane
@@ -487,7 +490,7 @@ __global__ void k_zero3(float* __restrict__ a, float* __restrict__ b, float* __r
   }
 }
 
-__global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
+__global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    const double* __restrict__ z,
                                                    const int32_t* __restrict__ cs, Grid g,
@@ -519,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_desc_bwd(const double* __restrict__ x,
     const int hs = s - s0 < kBrickMax ? home[s - s0] : TileF32::kDummy;
     const float xi = t.px[hs], yi = t.py[hs], zi = t.pz[hs];
     const int64_t oi = io.perm ? (int64_t)io.perm[s] : (int64_t)s;
-    float Ki[68];
+    float Ki[84];
     adjoint_coef(io.dEdG + oi * kNFeat, io.mom + oi * (2 * kNMom), Ki);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     const int ng = (tl.cnt[s] + 3) >> 2;
@@ -627,7 +630,7 @@ hipError_t desc_backward(const double* x, const double* y, const double* z,
   DescIO io{nullptr, const_cast<float*>(mom), dEdG, perm, fx, fy, fz};
   if (!zeroed)
     hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
-  const unsigned threads = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
+  const unsigned threads = 2 * tl.threads < 512 ? 2 * tl.threads : 512;
   hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid(g)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);
   return hipGetLastError();
