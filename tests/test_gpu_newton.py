@@ -77,6 +77,28 @@ def test_half_forces_energy_virial(name, precision, shift):
             assert abs(f2[3][0].item() - ref["pe"]) <= 1e-9 * abs(ref["pe"]) + 1e-12
 
 
+def test_half_reaction_beyond_the_fixed_point_range():
+    """A pair 0.47 sigma apart has a force component above 2^19, which the FP32
+    half pass adds to the output directly instead of through its 64-bit
+    fixed-point LDS sums: the forces still meet the oracle's bars."""
+    pos, box = CASES["sc1000_jitter"]
+    pos = pos.copy()
+    pos[1] = pos[0] + np.array([0.47, 0.0, 0.0])  # the whole force on one component
+    ref = olj.lj_forces(pos, box, 2.5, shift="none")
+    assert np.max(np.abs(ref["F"])) > 2.0 ** 19
+    sim = _sim(pos.shape[0], box, rc=2.5, skin=0.3, precision="fp32", max_nb=256)
+    x, y, z = split_dev(pos)
+    sim.build(x, y, z)
+    fx, fy, fz = sim.forces(x, y, z)[:3]
+    F = torch.stack([fx, fy, fz], 1).double().cpu().numpy()
+    g, m = force_errors(F, ref["F"])
+    assert g <= 1e-5 and m <= 1e-5, (g, m)
+    # every other atom (forces of order one) within the bar on its own scale
+    rest = np.arange(2, pos.shape[0])
+    gr, mr = force_errors(F[rest], ref["F"][rest])
+    assert gr <= 1e-5 and mr <= 1e-5, (gr, mr)
+
+
 def test_half_backward_is_minus_force():
     pos, box = CASES["grid_noncubic_4913"]
     sim = _sim(pos.shape[0], box, rc=2.5, skin=0.3, precision="fp64")

@@ -169,6 +169,30 @@ def test_fused_forces_match_three_calls(config):
         P.mdpl_mlp_forces(sim, m.weights(), x, y, z, small, b1["e"], b1["fx"], b1["fy"], b1["fz"])
 
 
+def test_backward_terms_beyond_the_fixed_point_range(config):
+    """With e_sd scaled by 2^27 every pair term of the descriptor backward is
+    above 2^19 and bypasses the 64-bit fixed-point LDS sums (direct device
+    atomics); the forces are the unscaled ones times 2^27 (the scaling is
+    exact in FP32, so only the summation differs)."""
+    from paper_1704_03329_amd.sim import soa
+    from paper_1704_03329_amd import potential as P
+
+    pos, box = config
+    n = pos.shape[0]
+    sim = _sim(n, box)
+    x, y, z = soa(torch.from_numpy(pos).cuda())
+    m = _model(P.descriptors(sim, torch.from_numpy(pos).cuda()),
+               torch.from_numpy(np.linspace(-6, -3, n)).cuda())
+    sim.build(x, y, z)
+    F0 = torch.stack(m.forces(sim, x, y, z)[1:], 1).double().cpu().numpy()
+    scale = 2.0 ** 27
+    m.e_sd = m.e_sd * scale
+    F1 = torch.stack(m.forces(sim, x, y, z)[1:], 1).double().cpu().numpy()
+    assert np.median(np.abs(F1)) > 2.0 ** 19
+    # the bar of the backward (its pair terms now summed by FP32 atomics throughout)
+    assert _rel(F1 / scale, F0) <= 1e-4
+
+
 def test_train_gradient_and_adam_match_oracle(config):
     from paper_1704_03329_amd import potential as P
 
