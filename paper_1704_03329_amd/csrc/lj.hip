@@ -62,9 +62,8 @@ __device__ __forceinline__ double fused_kick(const ForceOut& out, int64_t s, dou
   return k;
 }
 
-// FP64 pair arithmetic of the FP64 passes and of the energy and virial of
-// every pass (one definition, so that the plain and the energy pass of the
-// FP64 mode give the same forces): the reciprocal of d2 by the hardware
+// FP64 pair arithmetic of the FP64 passes (one definition, so that their
+// plain and energy passes give the same forces): the reciprocal of d2 by the hardware
 // estimate and two Newton steps (a few ulp), s6 = (s^2/d2)^3 and the force
 // factor f/dr = 48 eps s6 (s6 - 1/2) / d2.
 __device__ __forceinline__ double lj_inv64(double d2) {
@@ -542,12 +541,33 @@ void k_lj_force32_plain(const double* __restrict__ x, const double* __restrict__
   if (out.fuse && out.track.ring) block_track(out.track, vmax2, vred);
 }
 
+// s6 = (sigma^2 / d2)^3 in FP64, the reciprocal of d2 by two Newton steps
+// from the FP32 reciprocal of d2f that the pair's force factor takes anyway
+// (d2f: the FP32 square distance of the same pair).  Each step squares the
+// relative error of the seed, about 2^-18 sigma / r from the rounding of the
+// tile coordinates, so that the result is as accurate as the hardware FP64
+// reciprocal's two steps down to r of about 0.05 sigma (a pair energy of
+// 10^16 eps) and still within 2e-14 at 0.01 sigma.  This takes the FP64
+// reciprocal, a quarter-rate instruction, out of the energy pass's loop.
+__device__ __forceinline__ double lj_s6_seeded(double d2, float seed, const LJConst& c) {
+#pragma clang fp contract(off)
+  double inv = (double)seed;
+  inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
+  inv = __builtin_fma(inv, __builtin_fma(-d2, inv, 1.0), inv);
+  const double s2 = c.sigma2 * inv;
+  return s2 * s2 * s2;
+}
+
 // Energy FP32 pass: the FP64 image positions in the tile (energy and virial
 // are FP64 per pair); the FP32 coordinates of each partner are formed from
 // them with the plain tile's conversion, the pairs summed by the same lane
-// groups, and every entry classified by the exact rule.
+// groups, and every entry classified by the exact rule.  Workgroups of
+// kEnergyThreads: two share a CU (LDS: two FP64 tiles) at six waves per SIMD,
+// which leaves 80 VGPRs, enough for the pair loop without spills (the
+// 1024-thread shape, at 64 VGPRs, spilled ten and ran 5 % slower).
+constexpr int kEnergyThreads = 768;
 template <typename OT>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ __launch_bounds__(kEnergyThreads) __attribute__((amdgpu_waves_per_eu(6)))
 void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict__ y,
                          const double* __restrict__ z, const int32_t* __restrict__ cs, Grid g,
                          TileList tl, LJConst c, F32Const k, ForceOut out) {
@@ -570,7 +590,7 @@ void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict_
   double scale = out.scale;
   if (out.scale_dev) scale *= *out.scale_dev;
   double e = 0.0, w = 0.0, ke = 0.0, vmax2 = 0.0;
-  const double w24 = 24.0 * c.eps;
+  const double w24 = 24.0 * c.eps, e2 = 2.0 * c.eps, hshift = 0.5 * c.shift_v;
   for (int slot = threadIdx.x; slot < npart * 2 + kGroupWidth; slot += blockDim.x) {
     const int p0 = (slot / kGroupWidth) * (kGroupWidth >> 1);
     if (p0 >= npart) break;
@@ -582,7 +602,8 @@ void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict_
     const int ngroups = (tl.cnt[s] + 3) >> 2;
     const uint64_t* __restrict__ col = tl.nbr + s;
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    double ei = 0.0;
+    double s12 = 0.0, s6s = 0.0;  // sums of s6^2 and s6 over the pairs in range
+    int nin = 0;                  // and their number
     for (int gi = lg.part; gi < ngroups; gi += lg.T) {
       const uint64_t word = col[(int64_t)gi * tl.stride];
 #pragma unroll
@@ -599,18 +620,24 @@ void k_lj_force32_energy(const double* __restrict__ x, const double* __restrict_
         const double d2 = d2_image(xs, ys, zs, qx, qy, qz);
         const bool lo = d2f < k.r2lo, hi = d2f < k.r2hi;
         const bool in = lo != hi ? d2 < c.rc2 : lo;
-        // pair energy and virial in FP64; half of the pair's r f(r), which
-        // is 48 eps s6 (s6 - 1/2) with s6 = (sigma^2 / r^2)^3
-        const double s2 = c.sigma2 * lj_inv64(d2);
-        const double s6 = s2 * s2 * s2;
-        ei += in ? 0.5 * lj_v64(s6, c) : 0.0;
-        w += in ? w24 * (s6 * (s6 - 0.5)) : 0.0;
+        // the FP32 force factor, then s6 in FP64 from the same reciprocal
+        // (zero for an entry out of range); the pair energies and virial
+        // terms follow from the sums of s6^2 and s6 after the loop
         const float gf = lj_g32(d2f, in, k);
+        const double s6r = lj_s6_seeded(d2, __builtin_amdgcn_rcpf(in ? d2f : 3.0e38f), c);
+        const double s6 = in ? s6r : 0.0;
+        s12 = __builtin_fma(s6, s6, s12);
+        s6s += s6;
+        nin += in ? 1 : 0;
         ax = __builtin_fmaf(gf, dx, ax);
         ay = __builtin_fmaf(gf, dy, ay);
         az = __builtin_fmaf(gf, dz, az);
       }
     }
+    // the lane's pair energies, half of each pair's 4 eps (s6^2 - s6) + shift,
+    // and its virial terms, half of each pair's r f(r) = 48 eps (s6^2 - s6/2)
+    w = __builtin_fma(w24, __builtin_fma(-0.5, s6s, s12), w);
+    double ei = __builtin_fma(e2, s12 - s6s, hshift * (double)nin);
     ax = group_sum(ax, lg.T);
     ay = group_sum(ay, lg.T);
     az = group_sum(az, lg.T);
@@ -724,9 +751,8 @@ hipError_t lj_force(const double* x, const double* y, const double* z, const int
     case 1: {
       const F32Const k = f32_const(g, c);
       const dim3 grid(tile_grid(g));
-      const unsigned two = 2 * tl.threads < 1024 ? 2 * tl.threads : 1024;
       if (energy)
-        hipLaunchKernelGGL((k_lj_force32_energy<float>), grid, dim3(two), 0, st, x, y, z,
+        hipLaunchKernelGGL((k_lj_force32_energy<float>), grid, dim3(kEnergyThreads), 0, st, x, y, z,
                            cell_start, g, tl, c, k, out);
       else
         hipLaunchKernelGGL((k_lj_force32_plain<float>), grid, dim3(kPlainThreads), 0, st, x, y, z,
