@@ -490,7 +490,12 @@ __global__ void k_zero3(float* __restrict__ a, float* __restrict__ b, float* __r
   }
 }
 
-__global__ __launch_bounds__(512) void k_desc_bwd(const double* __restrict__ x,
+// Workgroups of up to kBwdThreads: the fixed-point accumulators make the LDS
+// of one workgroup fill most of a CU, so its own waves are all the latency
+// hiding there is; at 161 VGPRs three waves per SIMD fit (768 threads: 197 ->
+// 183 us against 512 at N = 262144).
+constexpr int kBwdThreads = 768;
+__global__ __launch_bounds__(kBwdThreads) void k_desc_bwd(const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    const double* __restrict__ z,
                                                    const int32_t* __restrict__ cs, Grid g,
@@ -630,7 +635,7 @@ hipError_t desc_backward(const double* x, const double* y, const double* z,
   DescIO io{nullptr, const_cast<float*>(mom), dEdG, perm, fx, fy, fz};
   if (!zeroed)
     hipLaunchKernelGGL(k_zero3, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, fx, fy, fz, n);
-  const unsigned threads = 2 * tl.threads < 512 ? 2 * tl.threads : 512;
+  const unsigned threads = 2 * tl.threads < kBwdThreads ? 2 * tl.threads : kBwdThreads;
   hipLaunchKernelGGL(k_desc_bwd, dim3(tile_grid(g)), dim3(threads), 0, st, x, y,
                      z, cell_start, g, tl, rc, io);
   return hipGetLastError();
