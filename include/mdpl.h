@@ -169,7 +169,8 @@ mdpl_status mdpl_sim_destroy(mdpl_sim* sim);
  * and the list is that of the folded positions, tested exactly as
  * (dx*dx + dy*dy) + dz*dz < (rc+skin)^2 in double with the conditional
  * minimum image dx -/+ L.  Particles are counting-sorted by cell into
- * workspace copies; the caller's arrays are not modified. */
+ * workspace copies (with full lists, each cell's particles in the lower half
+ * of the cell along x first); the caller's arrays are not modified. */
 mdpl_status mdpl_build(mdpl_sim* sim, const double* x, const double* y, const double* z);
 
 /* Copy the list of the last mdpl_build as directed pairs (i, j) in the

@@ -199,6 +199,7 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += align256(2 * (size_t)((p->max_nb + 3) & ~3) * (size_t)npad);  // nbr (16-bit tile indices)
   b += align256(4 * (size_t)npad);             // cnt
   b += align256(4 * (size_t)kTabInts * (size_t)g.nbricks);  // tile tables
+  b += align256(4 * (size_t)(g.nkeys + 1));                 // lower-x-half counts
   b += align256(4 * (size_t)(n + 1));          // offsets
   b += align256(8 * (size_t)(3 * nblk + 2));   // partials
   b += 2 * align256(8 * (size_t)track_slots(n, g));  // the rule's per-workgroup maxima
@@ -206,6 +207,10 @@ size_t lj_ws_bytes(const mdpl_lj_params* p, const Grid& g) {
   b += align256(4 * 8 * (size_t)g.nbricks);   // brick order of the tile kernels
   return b;
 }
+
+// The per-cell counts of the lower x half, when the list build may use them
+// (full lists whose cells are wider than the list radius along x).
+static int32_t* list_xlow(const mdpl_sim* s) { return s->tl.xlow; }
 
 static bool thin_brick(const Grid& g, int b) {
   const int bx = b % g.nb[0], by = (b / g.nb[0]) % g.nb[1], bz = b / (g.nb[0] * g.nb[1]);
@@ -416,6 +421,12 @@ mdpl_status mdpl_sim_create(const mdpl_lj_params* p, void* workspace, size_t byt
   s->tl.half = p->pairs == MDPL_PAIRS_HALF;
   s->tl.cells = p->pairs == MDPL_PAIRS_CELLS;
   s->tl.threads = threads;
+  s->tl.xlow = take<int32_t>(w, 4 * (size_t)(s->g.nkeys + 1));
+  // a particle's far half of the next cell along x lies beyond the list
+  // radius only if the cell is wider than that radius (with room for the
+  // rounding of the FP64 test)
+  if (s->tl.half || s->tl.cells || !(p->box[0] / s->g.nc[0] > rext * (1.0 + 1e-9)))
+    s->tl.xlow = nullptr;
   s->offsets = take<int32_t>(w, 4 * (size_t)(n + 1));
   s->nblk = (int)(div_up(n, 256) > s->g.nbricks ? div_up(n, 256) : s->g.nbricks);
   s->partials = take<double>(w, 8 * (size_t)(3 * s->nblk + 2));
@@ -503,7 +514,8 @@ mdpl_status mdpl_build(mdpl_sim* s, const double* x, const double* y, const doub
   if (!s || !x || !y || !z) return MDPL_EINVAL;
   s->resume.valid = false;
   int32_t *skeys, *svals;
-  HIP_TRY(bin_particles(x, y, z, s->n, s->g, s->sort, s->cell_start, &skeys, &svals, s->st));
+  HIP_TRY(bin_particles(x, y, z, s->n, s->g, s->sort, s->cell_start, &skeys, &svals, s->st,
+                        list_xlow(s)));
   HIP_TRY(hipMemcpyAsync(s->perm, svals, 4 * (size_t)s->n, hipMemcpyDeviceToDevice, s->st));
   s->skeys = skeys;
   HIP_TRY(gather_positions(x, y, z, s->perm, s->n, s->sx, s->sy, s->sz, s->p.box, true, s->st));
@@ -793,7 +805,7 @@ mdpl_status run_loop(mdpl_sim* s, StateArrays user, int64_t nsteps, int32_t samp
     }
     int32_t *skeys, *svals;
     HIP_TRY(bin_particles(cur.x, cur.y, cur.z, n, s->g, s->sort, s->cell_start, &skeys, &svals,
-                          s->st));
+                          s->st, list_xlow(s)));
     HIP_TRY(reorder_state(cur, svals, n, s->fbytes, s->p.box, other, s->xb, s->yb, s->zb,
                           s->bound, s->st));
     StateArrays t = cur;

@@ -71,16 +71,55 @@ __device__ __forceinline__ int cell_coord(double x, double L, double inv_side, i
   return q >= (double)nc ? nc - 1 : 0;
 }
 
+// The particles of each cell in two runs, the lower half of the cell along x
+// first (each run in sorted order, so the order stays deterministic), and
+// the length of the first run.  The half comes with each sorted value (its
+// top bit, set by k_cell_keys for the upper half).  A group of 16 lanes per
+// cell, a particle per lane (16 at a time), four cells per wave.
+constexpr int kPartLanes = 16;
+__global__ __launch_bounds__(256) void k_xhalf_partition(const int32_t* __restrict__ cs, int nkeys,
+                                                         const int32_t* __restrict__ vin,
+                                                         int32_t* __restrict__ vout,
+                                                         int32_t* __restrict__ xlow) {
+  const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kPartLanes);
+  if (c >= nkeys) return;
+  const int lane = (int)threadIdx.x & 63, sub = lane % kPartLanes;
+  const unsigned long long group = ((1ull << kPartLanes) - 1) << (lane - sub);
+  const unsigned long long below = ((1ull << lane) - 1) & group;
+  const int b = cs[c], e = cs[c + 1];
+  int lo = 0;  // the cell's lower-half particles
+  for (int s0 = b; s0 < e; s0 += kPartLanes) {
+    const bool has = s0 + sub < e;
+    lo += __popcll(__ballot(has && vin[has ? s0 + sub : b] >= 0) & group);
+  }
+  if (sub == 0) xlow[c] = lo;
+  int nl = 0, nu = 0;  // placed so far
+  for (int s0 = b; s0 < e; s0 += kPartLanes) {
+    const bool has = s0 + sub < e;
+    const int v = has ? vin[s0 + sub] : 0;
+    const bool low = has && v >= 0;
+    const unsigned long long ml = __ballot(low) & group, mu = __ballot(has && !low) & group;
+    if (has)
+      vout[low ? b + nl + __popcll(ml & below) : b + lo + nu + __popcll(mu & below)] =
+          v & 0x7fffffff;
+    nl += __popcll(ml);
+    nu += __popcll(mu);
+  }
+}
+
 __global__ void k_cell_keys(const double* __restrict__ x, const double* __restrict__ y,
                             const double* __restrict__ z, int64_t n, Grid g,
-                            int32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                            int32_t* __restrict__ keys, int32_t* __restrict__ vals, int xbit) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int cx = cell_coord(x[i], g.box[0], g.inv_side[0], g.nc[0]);
+  // xbit: the top bit of the value marks the upper half of the cell along x
+  // (decided on the quotient that gave the cell index)
+  const bool upper = xbit && !(fold(x[i], g.box[0]) * g.inv_side[0] - (double)cx < 0.5);
   int cy = cell_coord(y[i], g.box[1], g.inv_side[1], g.nc[1]);
   int cz = cell_coord(z[i], g.box[2], g.inv_side[2], g.nc[2]);
   keys[i] = cell_key(g, cx, cy, cz);
-  vals[i] = (int32_t)i;
+  vals[i] = (int32_t)((uint32_t)i | (upper ? 0x80000000u : 0u));
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const int32_t* __restrict__ keys,
@@ -246,9 +285,10 @@ hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* b
 
 hipError_t bin_particles(const double* x, const double* y, const double* z, int64_t n,
                          const Grid& g, SortBufs& s, int32_t* cell_start, int32_t** keys_out,
-                         int32_t** vals_out, hipStream_t st) {
+                         int32_t** vals_out, hipStream_t st, int32_t* xlow) {
   const unsigned nb = (unsigned)div_up(n, 256);
-  hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, st, x, y, z, n, g, s.keys[0], s.vals[0]);
+  hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, st, x, y, z, n, g, s.keys[0], s.vals[0],
+                     xlow ? 1 : 0);
   int bits = 1;
   while ((1ll << bits) < (long long)g.nkeys) ++bits;
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
@@ -272,6 +312,11 @@ hipError_t bin_particles(const double* x, const double* y, const double* z, int6
                      cell_start);
   *keys_out = s.keys[cur];
   *vals_out = s.vals[cur];
+  if (xlow) {
+    hipLaunchKernelGGL(k_xhalf_partition, dim3((unsigned)div_up((int64_t)g.nkeys * kPartLanes, 256)), dim3(256), 0, st,
+                       cell_start, g.nkeys, s.vals[cur], s.vals[cur ^ 1], xlow);
+    *vals_out = s.vals[cur ^ 1];
+  }
   return hipGetLastError();
 }
 

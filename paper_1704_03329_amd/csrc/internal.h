@@ -69,7 +69,7 @@ void sort_carve(char*& p, int64_t n, SortBufs* s);
 // (one of the two ping-pong buffers) and cell_start[0..ncells] is filled.
 hipError_t bin_particles(const double* x, const double* y, const double* z, int64_t n,
                          const Grid& g, SortBufs& s, int32_t* cell_start, int32_t** keys_out,
-                         int32_t** vals_out, hipStream_t st);
+                         int32_t** vals_out, hipStream_t st, int32_t* xlow = nullptr);
 
 // Exclusive prefix sum of n int32 values into out (may alias in).  Uses
 // blocksums scratch of at least div_up(n, 1024) + 1 entries.  Also writes
@@ -149,6 +149,9 @@ struct TileList {
   int threads;      // workgroup size of the tile kernels
   int half;         // 1: each pair once (Newton's third law), tiles of kTileMaxHalf slots
   int cells;        // 1: no list; the pair loop scans the cell stencil (nbr and cnt unused)
+  // per cell key, its particles in the lower half of the cell along x (they
+  // come first in the cell); null: the list build scans whole stencil rows
+  int32_t* xlow;
 };
 hipError_t build_tile_nlist(const double* x, const double* y, const double* z,
                             const int32_t* skeys, const int32_t* cell_start, const Grid& g,

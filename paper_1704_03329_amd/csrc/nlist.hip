@@ -11,7 +11,9 @@
 // Two builders:
 //  * the LJ list: one workgroup per brick stages its tile (stored positions,
 //    no images) in LDS, one wave per home cell tests the 27 tile cells of its
-//    stencil; entries are 16-bit tile byte offsets (16 x slot), column-major, so the force
+//    stencil (a full list: each cell's particles of the lower half along x
+//    first, so that a particle skips the half of the next or previous cell
+//    along x that lies beyond the list radius, 5/6 of each stencil row); entries are 16-bit tile byte offsets (16 x slot), column-major, so the force
 //    pass reads one coalesced word per four neighbours.  A half list (each
 //    pair once, Newton's third law) keeps j in the list of i only if j's tile
 //    index is larger (tile.h): four of the nine stencil rows whole, and the
@@ -130,9 +132,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     float guard, TileList tl, uint32_t* __restrict__ flags, int32_t* __restrict__ maxcount) {
   __shared__ TS t;
   __shared__ int acnt[kBrickMax];
+  __shared__ int tlow[kTileCells];  // per tile cell, its particles in the lower x half
   const int brick = brick_of_block(g);
   if (brick >= g.nbricks) return;
-  const int total = tile_cells(g, brick, cs, t, HALF);
+  const bool xh = !HALF && tl.xlow != nullptr;
+  const int total = tile_cells(g, brick, cs, t, HALF, tl.xlow, xh ? tlow : nullptr);
   if (!HALF && tl.tab) tile_tables_store(g, t, tl.tab + (int64_t)brick * kTabInts);
   const int s0 = cs[brick * g.V], s1 = cs[(brick + 1) * g.V];
   const int nbrick = s1 - s0;
@@ -215,6 +219,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       q.base = half + (int64_t)(ok ? s : 0) * 4;
       q.stride4 = (uint32_t)(tl.stride * 4);
       q.pitch = (uint32_t)(tl.stride * 8);
+      // a particle in the lower x half of its cell skips the upper half of
+      // the next cell along x, one in the upper half the lower half of the
+      // previous cell: more than a cell width, which exceeds the list
+      // radius, away along x alone
+      const bool lower = xh && a < tlow[tc0];
+      const bool upper = xh && !lower;
       for (int oz = -1; oz <= 1; ++oz) {
         for (int oy2 = -1; oy2 <= 1; ++oy2) {
           // a stencil row: three consecutive tile cells, one contiguous index range
@@ -222,9 +232,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           if (!ok) continue;
           // half list: only tile indices past the particle's own (rows below it are empty)
           if (HALF && (oz < 0 || (oz == 0 && oy2 < 0))) continue;
-          int ub = t.prefix[tcl];
+          int ub = t.prefix[tcl] + (upper ? tlow[tcl] : 0);
           if (HALF && ub <= self) ub = self + 1;
-          int ue = t.prefix[tcl + 3];
+          int ue = lower ? t.prefix[tcl + 2] + tlow[tcl + 2] : t.prefix[tcl + 3];
           ue = ue < TS::kCap ? ue : TS::kCap;
           scan_range<4, HALF ? kHalfShift : kFullShift, A24>(t, ub + k, ue, q);
         }

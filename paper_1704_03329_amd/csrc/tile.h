@@ -120,7 +120,8 @@ __device__ __forceinline__ void brick_coords(const Grid& g, int brick, int& bx, 
 // first cell are left empty.  Ends with a barrier.
 template <typename TS>
 __device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __restrict__ cs, TS& t,
-                                 bool half = false) {
+                                 bool half = false, const int32_t* __restrict__ xlow = nullptr,
+                                 int* tlow = nullptr) {
   const int TX = g.B[0] + 2, TY = g.B[1] + 2, TZ = g.B[2] + 2;
   const int ntc = TX * TY * TZ;
   int bx, by, bz;
@@ -137,6 +138,7 @@ __device__ inline int tile_cells(const Grid& g, int brick, const int32_t* __rest
     const int key = cell_key(g, cx, cy, cz);
     const int b = cs[key];
     t.src[tc] = b;
+    if (tlow) tlow[tc] = xlow[key];
     t.prefix[tc + 1] = tc < first ? 0 : cs[key + 1] - b;
     // bit 6: a cell of the brick itself (inside the box; a partial brick's
     // missing cells are images of other bricks' cells)
