@@ -61,6 +61,16 @@ def _cases():
     g[lo, 0] += gb[0]  # unfolded images just above the face
     out["grid_unfolded_2457"] = (g, gb)
     out["grid_sparse_36"] = _jittered_grid((3, 3, 4), 2.9, 0.2, 26)
+    # cells within 1e-9 of the list radius (three of 2.8 (1 + 5e-10); the grid
+    # takes cells of at least 1 + 1e-10 radii): the build scans whole stencil
+    # rows instead of skipping half-cells along x
+    p, b = _jittered_grid((6, 6, 6), 1.4, 0.2, 27)
+    out["grid_cell_at_radius_216"] = (p, b * (1.0 + 5e-10))
+    # particles on the cell and half-cell boundaries along x (cells 2.9 wide)
+    k = np.arange(6) * 1.45
+    zz, yy, xx = np.meshgrid(k + 0.3, k + 0.1, k, indexing="ij")
+    out["half_cell_boundaries_216"] = (np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1),
+                                       np.array([8.7, 8.7, 8.7]))
     return out
 
 
